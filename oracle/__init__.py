@@ -1,0 +1,223 @@
+"""CPU oracle for the cell-loop assembler -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, single-threaded FP64 C implementation (``oracle.c``) of what
+the parallel loop computes: the global assembly sums of the Helmholtz-type
+bilinear form, the source linear form and the matrix-free action, with its own
+sparsity.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product library never does.
+
+Every function here follows the paper's definition of a parallel loop over
+cells with data gathered through Maps and INC contributions summed
+(PyOP2 section: "Parloops and kernels", "Access descriptors",
+"Matrix arguments").
+
+Parity unpinned: none of the functions below lacks a pin; the pins live in
+``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-std=c99", "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p; I = C.c_int; L64 = C.c_int64; D = C.c_double
+        L.oracle_gauss_jacobi.argtypes = [I, I, P, P]; L.oracle_gauss_jacobi.restype = I
+        L.oracle_simplex_rule.argtypes = [I, I, P, P]; L.oracle_simplex_rule.restype = I
+        L.oracle_nloc.argtypes = [I, I]; L.oracle_nloc.restype = I
+        L.oracle_basis.argtypes = [I, I, P, P, P]; L.oracle_basis.restype = None
+        L.oracle_element_matrix.argtypes = [I, I, P, P, D, D, P]; L.oracle_element_matrix.restype = I
+        L.oracle_element_vector.argtypes = [I, I, P, P, P]; L.oracle_element_vector.restype = I
+        L.oracle_sparsity.argtypes = [L64, I, P, I, P, L64, L64, P, P]; L.oracle_sparsity.restype = L64
+        L.oracle_assemble_mat.argtypes = [I, I, L64, P, P, P, P, D, D, P, P, L64, P, P]
+        L.oracle_assemble_mat.restype = I
+        L.oracle_assemble_vec.argtypes = [I, I, L64, P, P, P, P, L64, P, P]
+        L.oracle_assemble_vec.restype = I
+        L.oracle_apply_action.argtypes = [I, I, L64, P, P, P, P, D, D, P, L64, P, P]
+        L.oracle_apply_action.restype = I
+        L.oracle_mat_rows.argtypes = [I, I, L64, P, P, P, P, D, D, L64, L64, P, L64, P, P, P, P]
+        L.oracle_mat_rows.restype = L64
+        L.oracle_vec_rows.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, L64, L64, P, P, P]
+        L.oracle_vec_rows.restype = I
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# Form coefficients: (cstiff, cmass) of  cstiff*kappa grad u.grad v + cmass*u v
+FORMS = {"helmholtz": (1.0, 1.0), "laplace": (1.0, 0.0), "mass": (0.0, 1.0)}
+
+
+def gauss_jacobi(n: int, alpha: int):
+    t = np.zeros(n); w = np.zeros(n)
+    rc = lib().oracle_gauss_jacobi(n, alpha, _p(t), _p(w))
+    if rc:
+        raise RuntimeError(f"gauss_jacobi failed ({rc})")
+    return t, w
+
+
+def simplex_rule(dim: int, q: int):
+    pts = np.zeros((q ** dim, dim)); wts = np.zeros(q ** dim)
+    n = lib().oracle_simplex_rule(dim, q, _p(pts), _p(wts))
+    if n <= 0:
+        raise RuntimeError("simplex_rule failed")
+    return pts[:n], wts[:n]
+
+
+def nloc(dim: int, degree: int) -> int:
+    return lib().oracle_nloc(dim, degree)
+
+
+def basis(dim: int, degree: int, lam):
+    lam = _c(lam, np.float64)
+    n = nloc(dim, degree)
+    phi = np.zeros(n); dphi = np.zeros((n, dim + 1))
+    lib().oracle_basis(dim, degree, _p(lam), _p(phi), _p(dphi))
+    return phi, dphi
+
+
+def element_matrix(dim, degree, xv, kv, form="helmholtz"):
+    cs, cm = FORMS[form]
+    xv = _c(xv, np.float64); kv = _c(kv, np.float64)
+    n = nloc(dim, degree); A = np.zeros((n, n))
+    if lib().oracle_element_matrix(dim, degree, _p(xv), _p(kv), cs, cm, _p(A)):
+        raise RuntimeError("element_matrix failed")
+    return A
+
+
+def element_vector(dim, degree, xv, fv):
+    xv = _c(xv, np.float64); fv = _c(fv, np.float64)
+    n = nloc(dim, degree); b = np.zeros(n)
+    if lib().oracle_element_vector(dim, degree, _p(xv), _p(fv), _p(b)):
+        raise RuntimeError("element_vector failed")
+    return b
+
+
+def sparsity(rmap, nrows, cmap=None, ncols=None):
+    """Oracle CSR pattern (row_ptr int64, col_idx int32)."""
+    rmap = _c(rmap, np.int32)
+    cmap = rmap if cmap is None else _c(cmap, np.int32)
+    ncols = nrows if ncols is None else ncols
+    ncells = rmap.shape[0]
+    row_ptr = np.zeros(nrows + 1, dtype=np.int64)
+    L = lib()
+    nnz = L.oracle_sparsity(ncells, rmap.shape[1], _p(rmap), cmap.shape[1], _p(cmap),
+                            nrows, ncols, _p(row_ptr), None)
+    if nnz < 0:
+        raise ValueError(f"oracle sparsity failed ({nnz})")
+    col_idx = np.zeros(max(nnz, 1), dtype=np.int32)
+    nnz2 = L.oracle_sparsity(ncells, rmap.shape[1], _p(rmap), cmap.shape[1], _p(cmap),
+                             nrows, ncols, _p(row_ptr), _p(col_idx))
+    assert nnz2 == nnz
+    return row_ptr, col_idx[:nnz]
+
+
+def assemble_mat(dim, degree, cell_vertex, coords, cell_node, kappa, row_ptr, col_idx,
+                 form="helmholtz"):
+    cs, cm = FORMS[form]
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    k = _c(kappa, np.float64); rp = _c(row_ptr, np.int64); ci = _c(col_idx, np.int32)
+    nrows = rp.size - 1
+    vals = np.zeros(max(int(rp[-1]), 1)); absv = np.zeros_like(vals)
+    rc = lib().oracle_assemble_mat(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k),
+                                   cs, cm, _p(rp), _p(ci), nrows, _p(vals), _p(absv))
+    if rc:
+        raise RuntimeError(f"oracle assemble_mat failed ({rc})")
+    nnz = int(rp[-1])
+    return vals[:nnz], absv[:nnz]
+
+
+def assemble_vec(dim, degree, cell_vertex, coords, cell_node, f, nrows):
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    fv = _c(f, np.float64)
+    b = np.zeros(nrows); ab = np.zeros(nrows)
+    rc = lib().oracle_assemble_vec(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(fv),
+                                   nrows, _p(b), _p(ab))
+    if rc:
+        raise RuntimeError(f"oracle assemble_vec failed ({rc})")
+    return b, ab
+
+
+def apply_action(dim, degree, cell_vertex, coords, cell_node, kappa, x, nrows,
+                 form="helmholtz"):
+    cs, cm = FORMS[form]
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    k = _c(kappa, np.float64); xx = _c(x, np.float64)
+    y = np.zeros(nrows); ay = np.zeros(nrows)
+    rc = lib().oracle_apply_action(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k),
+                                   cs, cm, _p(xx), nrows, _p(y), _p(ay))
+    if rc:
+        raise RuntimeError(f"oracle apply_action failed ({rc})")
+    return y, ay
+
+
+def mat_rows(dim, degree, cell_vertex, coords, cell_node, kappa, nrows, rows,
+             form="helmholtz"):
+    """Assembled rows ``rows`` (distinct): list of (cols, vals, abs) per row."""
+    cs, cm = FORMS[form]
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    k = _c(kappa, np.float64); rows = _c(rows, np.int64)
+    cap = rows.size * 1024
+    ptr = np.zeros(rows.size + 1, dtype=np.int64)
+    cols = np.zeros(cap, dtype=np.int32); vals = np.zeros(cap); absv = np.zeros(cap)
+    tot = lib().oracle_mat_rows(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k), cs, cm,
+                                nrows, rows.size, _p(rows), cap, _p(ptr), _p(cols), _p(vals),
+                                _p(absv))
+    if tot < 0:
+        raise RuntimeError(f"oracle mat_rows failed ({tot})")
+    return [(cols[ptr[s]:ptr[s + 1]].copy(), vals[ptr[s]:ptr[s + 1]].copy(),
+             absv[ptr[s]:ptr[s + 1]].copy()) for s in range(rows.size)]
+
+
+def vec_rows(dim, degree, cell_vertex, coords, cell_node, f, nrows, rows):
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    fv = _c(f, np.float64); rows = _c(rows, np.int64)
+    out = np.zeros(rows.size); absv = np.zeros(rows.size)
+    rc = lib().oracle_vec_rows(0, dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(fv),
+                               0.0, 0.0, None, nrows, rows.size, _p(rows), _p(out), _p(absv))
+    if rc:
+        raise RuntimeError("oracle vec_rows failed")
+    return out, absv
+
+
+def action_rows(dim, degree, cell_vertex, coords, cell_node, kappa, x, nrows, rows,
+                form="helmholtz"):
+    cs, cm = FORMS[form]
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    k = _c(kappa, np.float64); xx = _c(x, np.float64); rows = _c(rows, np.int64)
+    out = np.zeros(rows.size); absv = np.zeros(rows.size)
+    rc = lib().oracle_vec_rows(1, dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k),
+                               cs, cm, _p(xx), nrows, rows.size, _p(rows), _p(out), _p(absv))
+    if rc:
+        raise RuntimeError("oracle action_rows failed")
+    return out, absv
