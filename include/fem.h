@@ -1,0 +1,244 @@
+/*
+ * fem.h -- C ABI of the MI355X cell-loop finite element assembler.
+ *
+ * The library implements, on one AMD Instinct MI355X (gfx950), the parallel
+ * loop of PyOP2 (Rathgeber et al., "Firedrake: automating the finite element
+ * method by composing abstractions", section "PyOP2"): a local kernel is
+ * executed for every cell of the mesh, reading coordinates and coefficients
+ * gathered through Maps (access descriptor READ) and adding its element
+ * tensor into a global sparse matrix (Mat) or vector (Dat) (access
+ * descriptor INC).  The vocabulary follows the paper's data model:
+ *
+ *   Set       -- a number of entities (cells, vertices, nodes)      (Sets)
+ *   Map       -- constant-arity table from one Set to another        (Maps)
+ *   Dat       -- values attached to the members of a Set             (Data)
+ *   Mat       -- sparse bilinear operator over a row and a column Set,
+ *                assembled through two Maps; only WRITE and INC      (Matrix arguments)
+ *   par_loop  -- for all e in E: kernel(f_0(m_0(e)), ..., f_n(m_n(e)))
+ *                                                          (Parloops and kernels)
+ *
+ * Argument roles follow the Firedrake layer ("Assembling forms"): the output
+ * tensor first, then the coordinate field, then the coefficients.
+ *
+ * Forms (integrand on each cell K, P_k Lagrange test v / trial u, P1
+ * coefficient fields):
+ *   FEM_HELMHOLTZ  kappa grad(u).grad(v) + u v
+ *   FEM_LAPLACE    kappa grad(u).grad(v)
+ *   FEM_MASS       u v
+ *   FEM_SOURCE     f v              (linear form)
+ *
+ * Memory, ownership, ordering
+ *   - Every pointer inside fem_map, fem_dat, fem_sparsity and fem_mat is a
+ *     DEVICE pointer owned by the caller; it must stay valid until the work
+ *     queued on the context stream has completed.
+ *   - fem_ctx and fem_plan are library-owned (create/destroy pairs).
+ *   - All work is queued on the context's HIP stream.  Calls that must
+ *     return a host-visible result synchronise that stream and say so:
+ *     fem_build_sparsity (counting pass returns nnz), fem_plan_create,
+ *     fem_renumber, fem_sync.  The assembly calls and the action never
+ *     synchronise and never allocate.
+ *
+ * Errors
+ *   - Every call returns fem_status; no exception crosses the ABI and the
+ *     library never aborts.  Argument errors are detected on the host before
+ *     anything is queued.  Out-of-range Map entries are detected on the device
+ *     by fem_build_sparsity and fem_plan_create (which read every entry) and
+ *     reported as FEM_E_RANGE.  Device faults surface as FEM_E_DEVICE at the
+ *     next synchronising call.  fem_last_error() describes the last failure.
+ *
+ * Local (per-cell) node order, shared by every Map of a P_k space:
+ *   vertices 0..d in the cell-to-vertex Map's order; then edges in
+ *   lexicographic order of local vertex pairs ((0,1),(0,2),(0,3),(1,2),(1,3),
+ *   (2,3) on a tetrahedron; (0,1),(0,2),(1,2) on a triangle), the two P3
+ *   nodes of an edge ordered from its lower local vertex; then P3
+ *   tetrahedron faces (0,1,2),(0,1,3),(0,2,3),(1,2,3) or the P3 triangle's
+ *   interior node.  Vector-valued spaces number DOF = node*dim + component
+ *   (Firedrake layer, "Function spaces and functions").
+ *
+ * Determinism: results are bitwise reproducible run to run on the same
+ * inputs and plan (the paper's colouring is deterministic, "Parloops and
+ * kernels"); every sum is taken in ascending cell order.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fem_status {
+    FEM_OK = 0,
+    FEM_E_ARG = 1,          /* bad argument: null pointer, size/arity mismatch */
+    FEM_E_RANGE = 2,        /* a Map entry outside its target Set               */
+    FEM_E_OVERFLOW = 3,     /* a count exceeds an index type of the library     */
+    FEM_E_UNSUPPORTED = 4,  /* (cell, degree, form, precision) not provided     */
+    FEM_E_NOMEM = 5,        /* device or host allocation failed                 */
+    FEM_E_DEVICE = 6        /* HIP runtime or kernel error                      */
+} fem_status;
+
+/* Access descriptors ("Access descriptors").  READ for inputs; a Mat or an
+ * output Dat accepts WRITE (overwrite with the assembled sum) or INC (add the
+ * assembled sum to the existing values). */
+typedef enum fem_access { FEM_READ = 0, FEM_WRITE = 1, FEM_INC = 2 } fem_access;
+
+typedef enum fem_cell { FEM_TRIANGLE = 2, FEM_TETRAHEDRON = 3 } fem_cell;
+
+/* Arithmetic of the element contraction.  FEM_FP64 is the only one provided
+ * by this version; the others return FEM_E_UNSUPPORTED. */
+typedef enum fem_prec { FEM_FP64 = 0, FEM_FP32 = 1, FEM_BF16 = 2, FEM_FP16 = 3 } fem_prec;
+
+typedef enum fem_kind {
+    FEM_MASS = 0, FEM_LAPLACE = 1, FEM_HELMHOLTZ = 2, FEM_SOURCE = 3
+} fem_kind;
+
+/* A Set: only a size ("Sets"). */
+typedef struct fem_set { int64_t size; } fem_set;
+
+/* A Map from->to of constant arity: values[e*arity + l] in [0, to->size),
+ * int32, row-major [from->size][arity], device memory ("Maps"). */
+typedef struct fem_map {
+    const fem_set *from;
+    const fem_set *to;
+    int32_t arity;
+    const int32_t *values;
+} fem_map;
+
+/* A Dat: set->size * dim float64 values, node-major [size][dim], device
+ * memory ("Data").  Coordinates are a Dat of dim = geometric dimension on the
+ * vertex Set. */
+typedef struct fem_dat {
+    const fem_set *set;
+    int32_t dim;
+    double *data;
+} fem_dat;
+
+/* CSR sparsity of a Mat: row_ptr int64 [nrows+1], col_idx int32 [nnz], columns
+ * of each row ascending and unique; structural zeros kept; device memory. */
+typedef struct fem_sparsity {
+    int64_t nrows, ncols, nnz;
+    int64_t *row_ptr;
+    int32_t *col_idx;
+} fem_sparsity;
+
+/* A Mat: float64 values[nnz] in the CSR order of sp, device memory. */
+typedef struct fem_mat {
+    const fem_sparsity *sp;
+    double *values;
+} fem_mat;
+
+/* The local kernel: form kind, cell shape, Lagrange degree of the test and
+ * trial space (1..3), value dimension of that space (1), contraction
+ * precision. */
+typedef struct fem_form {
+    fem_kind kind;
+    fem_cell cell;
+    int32_t degree;
+    int32_t dim;
+    fem_prec prec;
+} fem_form;
+
+/* par_loop data arguments other than the output: the iteration Set (cells),
+ * the coordinate field (a P1 vector Dat read through cell_vertex), the
+ * cell-to-node Map of the P_k space, and P1 coefficient Dats read through
+ * cell_vertex: coeff[0] is kappa for the bilinear forms and f for
+ * FEM_SOURCE. */
+typedef struct fem_args {
+    const fem_set *cells;
+    const fem_map *cell_vertex;
+    const fem_dat *coords;
+    const fem_map *cell_node;
+    const fem_dat *coeff[4];
+    int32_t ncoeff;
+} fem_args;
+
+typedef struct fem_ctx fem_ctx;
+typedef struct fem_plan fem_plan;
+
+/* Create a context on HIP device `device` queuing on `hip_stream` (a
+ * hipStream_t; NULL = the null stream). */
+fem_status fem_ctx_create(int device, void *hip_stream, fem_ctx **ctx);
+void fem_ctx_destroy(fem_ctx *ctx);
+fem_status fem_ctx_set_stream(fem_ctx *ctx, void *hip_stream);
+/* Text of the last failure on this context ("" if none); owned by ctx. */
+const char *fem_last_error(const fem_ctx *ctx);
+/* Synchronise the context stream; FEM_E_DEVICE on a pending device error. */
+fem_status fem_sync(fem_ctx *ctx);
+
+/*
+ * Sparsity of the Mat assembled through row Map rmap and column Map cmap
+ * (same source Set): row i holds every column that any cell incident to i
+ * reaches through cmap (paper: PyOP2 builds the sparsity OP2 lacks, from a
+ * pair of Maps; "Matrix arguments").  Two calls:
+ *   1. sp->col_idx == NULL: writes sp->row_ptr (caller-allocated, nrows+1)
+ *      and sets sp->nnz, sp->nrows = rmap->to->size, sp->ncols =
+ *      cmap->to->size.  Synchronises (nnz is returned to the host).
+ *   2. sp->col_idx != NULL (nnz entries, caller-allocated), row_ptr from the
+ *      first call: fills the columns.  Does not synchronise.
+ * FEM_E_RANGE if a Map entry is out of range, FEM_E_OVERFLOW if nnz or the
+ * incidence count does not fit the library's int32 column/entry indices.
+ * Temporary device memory is allocated and freed inside the call.
+ */
+fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap,
+                              fem_sparsity *sp);
+
+/*
+ * Execution plan of the deterministic INC for one (form, args) pair.
+ * With sp != NULL the plan serves fem_par_loop_assemble_mat on that
+ * sparsity; with sp == NULL it serves fem_par_loop_assemble_vec and
+ * fem_apply_action.  The plan partitions the rows of the output into
+ * contiguous blocks, each owned by one workgroup that gathers every
+ * contribution to its rows in ascending cell order (conflict-free INC without
+ * atomics; "Access descriptors": only INC needs a schedule).  It references
+ * the Maps' device arrays: rebuild it if their contents change.  Synchronises;
+ * allocates device memory owned by the plan.
+ */
+fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
+                           const fem_sparsity *sp, fem_plan **plan);
+void fem_plan_destroy(fem_plan *plan);
+/* Plan statistics: number of row blocks, total (block, cell) pairs, bytes of
+ * device memory held.  Any output pointer may be NULL. */
+fem_status fem_plan_info(const fem_plan *plan, int64_t *nblocks, int64_t *cell_visits,
+                         int64_t *device_bytes);
+
+/*
+ * A[rmap(c,i), cmap(c,j)] (+)= integral over cell c of the bilinear form, for
+ * every cell c (par_loop with the Mat argument INC'd through two Maps).
+ * acc = FEM_WRITE overwrites A->values with the sum, FEM_INC adds to them.
+ * Asynchronous on the context stream; allocates nothing.
+ */
+fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                     const fem_args *args, fem_mat *A, fem_access acc);
+
+/* b[cell_node(c,i)] (+)= integral over cell c of f v_i (FEM_SOURCE form). */
+fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                     const fem_args *args, fem_dat *b, fem_access acc);
+
+/* Matrix-free action y (+)= A x with A the assembled bilinear form, computed
+ * cell by cell without forming the CSR matrix (the paper's wave benchmark
+ * assembles exactly such an action, grad(v).grad(phi), every time step). */
+fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                            const fem_args *args, const fem_dat *x, fem_dat *y, fem_access acc);
+
+/*
+ * Locality renumbering (setup; the paper renumbers the mesh with RCM for
+ * cache locality, experiments section "Problem setup"): host int32 outputs
+ *   cell_perm[new]   = old cell    (size cells->size)
+ *   vertex_perm[new] = old vertex  (size cell_vertex->to->size)
+ *   node_perm[new]   = old node    (size cell_node->to->size)
+ * ordering cells by the Hilbert index of their centroid and vertices and
+ * nodes by the Hilbert index of their position, so that contiguous rows and
+ * cells are compact in space.  Any output may be NULL.  The caller applies
+ * the permutations to its inputs (outputs are then numbered in the new
+ * order); nothing is hidden inside the library.  Synchronises.
+ */
+fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args,
+                        int32_t *cell_perm, int32_t *vertex_perm, int32_t *node_perm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_H */

@@ -1,0 +1,658 @@
+// C ABI of the cell-loop assembler: validation, context, sparsity, plans,
+// renumbering and kernel dispatch.  See include/fem.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "fem_internal.h"
+
+namespace {
+
+fem_status fail(fem_ctx *ctx, fem_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+fem_status hip_fail(fem_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? FEM_E_NOMEM : FEM_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIPC(call, what)                                      \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+int nloc_of(int dim, int degree)
+{
+    if (degree < 1 || degree > 3) return -1;
+    if (dim == 2) return (degree + 1) * (degree + 2) / 2;
+    if (dim == 3) return (degree + 1) * (degree + 2) * (degree + 3) / 6;
+    return -1;
+}
+
+bool map_ok(const fem_map *m)
+{
+    return m && m->from && m->to && m->arity > 0 && m->from->size >= 0 && m->to->size >= 0 &&
+           (m->values || m->from->size == 0);
+}
+
+bool dat_ok(const fem_dat *d, const fem_set *set, int dim)
+{
+    return d && d->set && d->dim == dim && d->set->size == set->size && (d->data || set->size == 0);
+}
+
+// Device buffer freed at scope exit (setup paths only).
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    explicit DevBuf(hipStream_t st) : s(st) {}
+    hipError_t alloc(size_t bytes) { return hipMallocAsync(&p, bytes ? bytes : 8, s); }
+    ~DevBuf() { if (p) (void)hipFreeAsync(p, s); }
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+fem_status check_form(fem_ctx *ctx, const fem_form *f)
+{
+    if (!f) return fail(ctx, FEM_E_ARG, "form is NULL");
+    if (f->cell != FEM_TRIANGLE && f->cell != FEM_TETRAHEDRON)
+        return fail(ctx, FEM_E_UNSUPPORTED, "cell %d not supported", (int)f->cell);
+    if (f->degree < 1 || f->degree > 3)
+        return fail(ctx, FEM_E_UNSUPPORTED, "degree %d not supported (1..3)", f->degree);
+    if (f->dim != 1) return fail(ctx, FEM_E_UNSUPPORTED, "value dimension %d not supported", f->dim);
+    if (f->prec != FEM_FP64)
+        return fail(ctx, FEM_E_UNSUPPORTED, "precision %d not supported", (int)f->prec);
+    if (f->kind < FEM_MASS || f->kind > FEM_SOURCE)
+        return fail(ctx, FEM_E_UNSUPPORTED, "form kind %d not supported", (int)f->kind);
+    return FEM_OK;
+}
+
+fem_status check_args(fem_ctx *ctx, const fem_form *f, const fem_args *a, bool need_coeff)
+{
+    if (!a || !a->cells || !a->cell_vertex || !a->coords || !a->cell_node)
+        return fail(ctx, FEM_E_ARG, "args: cells, cell_vertex, coords and cell_node are required");
+    const int d = (int)f->cell;
+    const int nl = nloc_of(d, f->degree);
+    if (!map_ok(a->cell_vertex) || !map_ok(a->cell_node))
+        return fail(ctx, FEM_E_ARG, "args: malformed Map");
+    if (a->cells->size < 0) return fail(ctx, FEM_E_ARG, "args: negative cell count");
+    if (a->cell_vertex->from->size != a->cells->size || a->cell_node->from->size != a->cells->size)
+        return fail(ctx, FEM_E_ARG, "args: Maps must start from the cell Set");
+    if (a->cell_vertex->arity != d + 1)
+        return fail(ctx, FEM_E_ARG, "args: cell_vertex arity %d, expected %d", a->cell_vertex->arity, d + 1);
+    if (a->cell_node->arity != nl)
+        return fail(ctx, FEM_E_ARG, "args: cell_node arity %d, expected %d for degree %d",
+                    a->cell_node->arity, nl, f->degree);
+    if (!dat_ok(a->coords, a->cell_vertex->to, d))
+        return fail(ctx, FEM_E_ARG, "args: coords must be a dim-%d Dat on the vertex Set", d);
+    if (a->ncoeff < 0 || a->ncoeff > 4) return fail(ctx, FEM_E_ARG, "args: ncoeff out of range");
+    if (need_coeff) {
+        if (a->ncoeff < 1 || !dat_ok(a->coeff[0], a->cell_vertex->to, 1))
+            return fail(ctx, FEM_E_ARG, "args: coeff[0] must be a scalar P1 Dat on the vertex Set");
+    }
+    if (a->cells->size * (int64_t)nl > INT32_MAX || a->cell_node->to->size > INT32_MAX ||
+        a->cell_vertex->to->size > INT32_MAX)
+        return fail(ctx, FEM_E_OVERFLOW, "args: more than 2^31-1 cell-node entries or nodes");
+    return FEM_OK;
+}
+
+void form_coeffs(fem_kind k, double *cstiff, double *cmass)
+{
+    *cstiff = (k == FEM_LAPLACE || k == FEM_HELMHOLTZ) ? 1.0 : 0.0;
+    *cmass = (k == FEM_MASS || k == FEM_HELMHOLTZ) ? 1.0 : 0.0;
+}
+
+fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *name)
+{
+    int hflag = 0;
+    HIPC(hipMemsetAsync(dflag, 0, sizeof(int), ctx->stream), "memset");
+    HIPC(femk::check_range(m->values, m->from->size * (int64_t)m->arity, m->to->size, dflag, ctx->stream),
+         "range check");
+    HIPC(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "copy");
+    HIPC(hipStreamSynchronize(ctx->stream), "sync");
+    if (hflag) return fail(ctx, FEM_E_RANGE, "%s: a Map entry lies outside its target Set", name);
+    return FEM_OK;
+}
+
+void free_plan_arrays(fem_plan *p)
+{
+    void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->inc_ptr, p->ent, p->gpos};
+    for (void *q : arrs)
+        if (q) (void)hipFree(q);
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes, hipStream_t s)
+{
+    size_t n = src.size() * sizeof(T);
+    hipError_t e = hipMalloc((void **)dst, n ? n : 8);
+    if (e != hipSuccess) return e;
+    *bytes += n;
+    if (n) e = hipMemcpyAsync(*dst, src.data(), n, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+// ---- Hilbert index (J. Skilling, "Programming the Hilbert curve", 2004):
+// coordinates -> transposed Hilbert form -> bit-interleaved index.
+uint64_t hilbert_index(uint32_t X[3], int n, int b)
+{
+    const uint32_t M = 1u << (b - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < n; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < n; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[n - 1] & Q) t ^= Q - 1;
+    for (int i = 0; i < n; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int j = b - 1; j >= 0; --j)
+        for (int i = 0; i < n; ++i) h = (h << 1) | ((X[i] >> j) & 1u);
+    return h;
+}
+
+// Integer barycentric weights of local node l (sum = degree), following the
+// local node order of fem.h.
+void local_weights(int dim, int degree, std::vector<std::vector<int>> &W)
+{
+    const int nv = dim + 1;
+    W.clear();
+    for (int v = 0; v < nv; ++v) {
+        std::vector<int> w(nv, 0);
+        w[v] = degree;
+        W.push_back(w);
+    }
+    if (degree >= 2)
+        for (int a = 0; a < nv; ++a)
+            for (int b = a + 1; b < nv; ++b) {
+                std::vector<int> w(nv, 0);
+                if (degree == 2) {
+                    w[a] = 1; w[b] = 1; W.push_back(w);
+                } else {
+                    w[a] = 2; w[b] = 1; W.push_back(w);
+                    std::vector<int> w2(nv, 0);
+                    w2[a] = 1; w2[b] = 2; W.push_back(w2);
+                }
+            }
+    if (degree == 3)
+        for (int a = 0; a < nv; ++a)
+            for (int b = a + 1; b < nv; ++b)
+                for (int c = b + 1; c < nv; ++c) {
+                    std::vector<int> w(nv, 0);
+                    w[a] = w[b] = w[c] = 1;
+                    W.push_back(w);
+                }
+}
+
+void sfc_order(const std::vector<double> &pos, int dim, int64_t n, int32_t *perm)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int r = 0; r < dim; ++r) {
+            lo[r] = std::min(lo[r], pos[i * dim + r]);
+            hi[r] = std::max(hi[r], pos[i * dim + r]);
+        }
+    const int bits = dim == 3 ? 21 : 31;
+    const double top = (double)((1u << bits) - 1);
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t X[3] = {0, 0, 0};
+        for (int r = 0; r < dim; ++r) {
+            const double span = hi[r] > lo[r] ? hi[r] - lo[r] : 1.0;
+            double u = (pos[i * dim + r] - lo[r]) / span * top;
+            X[r] = (uint32_t)std::min(std::max(u, 0.0), top);
+        }
+        key[i] = {hilbert_index(X, dim, bits), (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t i = 0; i < n; ++i) perm[i] = key[i].second;
+}
+
+}  // namespace
+
+extern "C" {
+
+fem_status fem_ctx_create(int device, void *hip_stream, fem_ctx **out)
+{
+    if (!out) return FEM_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FEM_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return FEM_E_DEVICE;
+    fem_ctx *ctx = new (std::nothrow) fem_ctx;
+    if (!ctx) return FEM_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->num_cus = cus;
+    *out = ctx;
+    return FEM_OK;
+}
+
+void fem_ctx_destroy(fem_ctx *ctx) { delete ctx; }
+
+fem_status fem_ctx_set_stream(fem_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return FEM_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return FEM_OK;
+}
+
+const char *fem_last_error(const fem_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+fem_status fem_sync(fem_ctx *ctx)
+{
+    if (!ctx) return FEM_E_ARG;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "pending device error");
+    return FEM_OK;
+}
+
+fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, fem_sparsity *sp)
+{
+    if (!ctx) return FEM_E_ARG;
+    if (!map_ok(rmap) || !map_ok(cmap) || !sp || !sp->row_ptr)
+        return fail(ctx, FEM_E_ARG, "build_sparsity: malformed Map or NULL row_ptr");
+    if (rmap->from->size != cmap->from->size)
+        return fail(ctx, FEM_E_ARG, "build_sparsity: row and column Maps start from different Sets");
+    const int64_t ncells = rmap->from->size, nrows = rmap->to->size, ncols = cmap->to->size;
+    if (ncells * (int64_t)rmap->arity > INT32_MAX || ncells * (int64_t)cmap->arity > INT32_MAX ||
+        nrows > INT32_MAX || ncols > INT32_MAX)
+        return fail(ctx, FEM_E_OVERFLOW, "build_sparsity: more than 2^31-1 entries");
+    hipStream_t s = ctx->stream;
+    const bool counting = sp->col_idx == nullptr;
+    DevBuf flag(s), ptr(s), ent(s), tmp(s);
+    HIPC(flag.alloc(sizeof(int)), "alloc");
+    if (counting) {
+        fem_status st = range_check(ctx, rmap, flag.as<int>(), "row Map");
+        if (st != FEM_OK) return st;
+        st = range_check(ctx, cmap, flag.as<int>(), "column Map");
+        if (st != FEM_OK) return st;
+    }
+    HIPC(ptr.alloc(sizeof(int64_t) * (nrows + 1)), "alloc");
+    HIPC(ent.alloc(sizeof(int32_t) * (ncells * rmap->arity)), "alloc");
+    HIPC(tmp.alloc(sizeof(int32_t) * (nrows + 1)), "alloc");
+    HIPC(femk::build_incidence(rmap->values, ncells, rmap->arity, nrows, ptr.as<int64_t>(),
+                               ent.as<int32_t>(), tmp.as<int32_t>(), s),
+         "incidence");
+    HIPC(hipMemsetAsync(flag.p, 0, sizeof(int), s), "memset");
+    if (counting) {
+        HIPC(femk::row_columns(ptr.as<int64_t>(), ent.as<int32_t>(), rmap->arity, cmap->values,
+                               cmap->arity, nrows, tmp.as<int32_t>(), nullptr, nullptr, flag.as<int>(), s),
+             "row columns");
+        HIPC(femk::exclusive_scan(tmp.as<int32_t>(), sp->row_ptr, nrows, s), "scan");
+        int hflag = 0;
+        int64_t nnz = 0;
+        HIPC(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+        HIPC(hipMemcpyAsync(&nnz, sp->row_ptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
+        HIPC(hipStreamSynchronize(s), "sync");
+        if (hflag)
+            return fail(ctx, FEM_E_UNSUPPORTED, "build_sparsity: a row reaches more than 2048 candidate columns");
+        sp->nrows = nrows;
+        sp->ncols = ncols;
+        sp->nnz = nnz;
+    } else {
+        if (sp->nrows != nrows || sp->ncols != ncols)
+            return fail(ctx, FEM_E_ARG, "build_sparsity: sparsity was counted for other Maps");
+        HIPC(femk::row_columns(ptr.as<int64_t>(), ent.as<int32_t>(), rmap->arity, cmap->values,
+                               cmap->arity, nrows, nullptr, sp->row_ptr, sp->col_idx, flag.as<int>(), s),
+             "row columns");
+    }
+    return FEM_OK;
+}
+
+fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
+                           const fem_sparsity *sp, fem_plan **out)
+{
+    if (!ctx) return FEM_E_ARG;
+    if (!out) return fail(ctx, FEM_E_ARG, "plan_create: NULL output");
+    *out = nullptr;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    st = check_args(ctx, form, args, false);
+    if (st != FEM_OK) return st;
+    const bool is_mat = sp != nullptr;
+    const int dim = (int)form->cell, deg = form->degree, nl = nloc_of(dim, deg);
+    const int64_t ncells = args->cells->size, nrows = args->cell_node->to->size;
+    if (is_mat) {
+        if (!sp->row_ptr || sp->nrows != nrows || sp->ncols != nrows || (!sp->col_idx && sp->nnz > 0))
+            return fail(ctx, FEM_E_ARG, "plan_create: sparsity does not match the cell_node Map");
+        if (form->kind == FEM_SOURCE)
+            return fail(ctx, FEM_E_ARG, "plan_create: a Mat plan needs a bilinear form");
+    }
+    femk::Limits lim;
+    if (!femk::limits(dim, deg, is_mat, &lim))
+        return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: no kernel for this cell/degree");
+    hipStream_t s = ctx->stream;
+    DevBuf flag(s), ptr(s), ent(s), tmp(s);
+    HIPC(flag.alloc(sizeof(int)), "alloc");
+    st = range_check(ctx, args->cell_node, flag.as<int>(), "cell_node");
+    if (st != FEM_OK) return st;
+    st = range_check(ctx, args->cell_vertex, flag.as<int>(), "cell_vertex");
+    if (st != FEM_OK) return st;
+    HIPC(ptr.alloc(sizeof(int64_t) * (nrows + 1)), "alloc");
+    HIPC(ent.alloc(sizeof(int32_t) * (ncells * nl)), "alloc");
+    HIPC(tmp.alloc(sizeof(int32_t) * (nrows + 1)), "alloc");
+    HIPC(femk::build_incidence(args->cell_node->values, ncells, nl, nrows, ptr.as<int64_t>(),
+                               ent.as<int32_t>(), tmp.as<int32_t>(), s),
+         "incidence");
+    std::vector<int64_t> hptr(nrows + 1);
+    std::vector<int32_t> hent(ncells * nl);
+    std::vector<int64_t> hrp;
+    HIPC(hipMemcpyAsync(hptr.data(), ptr.p, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost, s), "copy");
+    if (!hent.empty())
+        HIPC(hipMemcpyAsync(hent.data(), ent.p, sizeof(int32_t) * hent.size(), hipMemcpyDeviceToHost, s), "copy");
+    if (is_mat) {
+        hrp.resize(nrows + 1);
+        HIPC(hipMemcpyAsync(hrp.data(), sp->row_ptr, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost, s),
+             "copy");
+    }
+    HIPC(hipStreamSynchronize(s), "sync");
+    if (is_mat && hrp[nrows] != sp->nnz)
+        return fail(ctx, FEM_E_ARG, "plan_create: row_ptr[nrows] differs from nnz");
+
+    // Greedy partition of the rows into contiguous blocks bounded by the
+    // rows a workgroup owns, the Mat values it can hold in LDS and the
+    // distinct cells its local index can address.  Keep at least ~2 blocks
+    // per CU when the problem is small.
+    int64_t rows_cap = lim.rows_per_block;
+    const int64_t want = 2 * (int64_t)ctx->num_cus;
+    if (nrows < rows_cap * want) rows_cap = std::max<int64_t>(1, (nrows + want - 1) / want);
+    std::vector<int32_t> blk_row0{0}, blk_cptr{0}, bcell;
+    std::vector<int32_t> stamp(ncells, -1), lpos(ncells, 0);
+    std::vector<uint16_t> hent16(hent.size());
+    int64_t max_row = 0;
+    if (is_mat)
+        for (int64_t r = 0; r < nrows; ++r) max_row = std::max(max_row, hrp[r + 1] - hrp[r]);
+    const int lbits = nl <= 4 ? 2 : nl <= 8 ? 3 : nl <= 16 ? 4 : 5;
+    int32_t b = 0;
+    int64_t rows = 0, slots = 0, cells = 0;
+    size_t first_cell = 0;
+    int64_t block_first_row = 0;
+    auto close_block = [&](int64_t next_row) {
+        std::sort(bcell.begin() + first_cell, bcell.end());
+        for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
+        for (int64_t r = block_first_row; r < next_row; ++r)
+            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                const int32_t e = hent[k];
+                hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
+            }
+        blk_row0.push_back((int32_t)next_row);
+        blk_cptr.push_back((int32_t)bcell.size());
+        first_cell = bcell.size();
+        block_first_row = next_row;
+        ++b;
+        rows = slots = cells = 0;
+    };
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t rs = is_mat ? hrp[r + 1] - hrp[r] : 0;
+        int64_t fresh = 0;
+        for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) fresh += stamp[hent[k] / nl] != b;
+        if (rows > 0 && (rows + 1 > rows_cap || slots + rs > lim.slot_cap * (int64_t)is_mat ||
+                         cells + fresh > lim.cell_cap)) {
+            close_block(r);
+            fresh = hptr[r + 1] - hptr[r];
+        }
+        if ((is_mat && rs > lim.slot_cap) || fresh > lim.cell_cap)
+            return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: row %lld is too long for one workgroup",
+                        (long long)r);
+        for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+            const int32_t c = hent[k] / nl;
+            if (stamp[c] != b) {
+                stamp[c] = b;
+                bcell.push_back(c);
+            }
+        }
+        ++rows;
+        slots += rs;
+        cells += fresh;
+    }
+    if (rows > 0) close_block(nrows);
+
+    fem_plan *p = new (std::nothrow) fem_plan;
+    if (!p) return fail(ctx, FEM_E_NOMEM, "plan_create: host allocation");
+    p->is_mat = is_mat;
+    p->dim = dim; p->degree = deg; p->nloc = nl;
+    p->ncells = ncells; p->nrows = nrows; p->nverts = args->cell_vertex->to->size;
+    p->nnz = is_mat ? sp->nnz : 0;
+    p->nblk = b;
+    p->lbits = lbits;
+    p->cell_visits = (int64_t)bcell.size();
+    p->cell_node = args->cell_node->values;
+    p->row_ptr = is_mat ? sp->row_ptr : nullptr;
+    std::vector<int32_t> inc32(nrows + 1);
+    for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(&p->blk_row0, blk_row0, &p->bytes, s);
+    if (e == hipSuccess) e = upload(&p->blk_cptr, blk_cptr, &p->bytes, s);
+    if (e == hipSuccess) e = upload(&p->bcell, bcell, &p->bytes, s);
+    if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
+    if (e == hipSuccess) e = upload(&p->ent, hent16, &p->bytes, s);
+    if (e == hipSuccess && is_mat) {
+        p->pos_bytes = max_row <= 256 ? 1 : 2;
+        if (max_row > 65536) {
+            free_plan_arrays(p);
+            delete p;
+            return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row has more than 65536 columns");
+        }
+        const int rowbytes = ((nl * p->pos_bytes + 3) / 4) * 4;
+        p->gstride = rowbytes / p->pos_bytes;
+        const size_t gbytes = (size_t)ncells * nl * rowbytes;
+        e = hipMalloc(&p->gpos, gbytes ? gbytes : 8);
+        if (e == hipSuccess) {
+            p->bytes += gbytes;
+            e = hipMemsetAsync(flag.p, 0, sizeof(int), s);
+        }
+        if (e == hipSuccess && gbytes)
+            e = hipMemsetAsync(p->gpos, 0, gbytes, s);
+        if (e == hipSuccess)
+            e = femk::positions(ptr.as<int64_t>(), ent.as<int32_t>(), nl, args->cell_node->values, nl, nrows,
+                                sp->row_ptr, sp->col_idx, p->gpos, p->pos_bytes, p->gstride, flag.as<int>(), s);
+        int hflag = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && hflag) {
+            free_plan_arrays(p);
+            delete p;
+            return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_plan_arrays(p);
+        delete p;
+        return hip_fail(ctx, e, "plan_create");
+    }
+    *out = p;
+    return FEM_OK;
+}
+
+void fem_plan_destroy(fem_plan *p)
+{
+    if (!p) return;
+    free_plan_arrays(p);
+    delete p;
+}
+
+fem_status fem_plan_info(const fem_plan *p, int64_t *nblocks, int64_t *cell_visits, int64_t *device_bytes)
+{
+    if (!p) return FEM_E_ARG;
+    if (nblocks) *nblocks = p->nblk;
+    if (cell_visits) *cell_visits = p->cell_visits;
+    if (device_bytes) *device_bytes = (int64_t)p->bytes;
+    return FEM_OK;
+}
+
+static fem_status check_plan(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                             bool want_mat)
+{
+    if (!plan) return fail(ctx, FEM_E_ARG, "plan is NULL");
+    if (plan->is_mat != (int)want_mat)
+        return fail(ctx, FEM_E_ARG, want_mat ? "a Mat plan (built with a sparsity) is required"
+                                             : "a Dat plan (built without a sparsity) is required");
+    if (plan->dim != (int)form->cell || plan->degree != form->degree)
+        return fail(ctx, FEM_E_ARG, "plan was built for another cell/degree");
+    if (plan->cell_node != args->cell_node->values || plan->ncells != args->cells->size ||
+        plan->nrows != args->cell_node->to->size || plan->nverts != args->cell_vertex->to->size)
+        return fail(ctx, FEM_E_ARG, "plan was built for other Maps");
+    return FEM_OK;
+}
+
+static femk::AsmArgs base_args(const fem_plan *plan, const fem_args *args)
+{
+    femk::AsmArgs a{};
+    a.plan = plan;
+    a.cell_vertex = args->cell_vertex->values;
+    a.coords = args->coords->data;
+    a.cell_node = args->cell_node->values;
+    return a;
+}
+
+fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                     const fem_args *args, fem_mat *A, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (form->kind == FEM_SOURCE) return fail(ctx, FEM_E_ARG, "assemble_mat needs a bilinear form");
+    const bool need_k = form->kind != FEM_MASS;
+    if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, true)) != FEM_OK) return st;
+    if (!A || !A->sp || (!A->values && plan->nnz > 0))
+        return fail(ctx, FEM_E_ARG, "assemble_mat: Mat without values");
+    if (A->sp->row_ptr != plan->row_ptr || A->sp->nnz != plan->nnz)
+        return fail(ctx, FEM_E_ARG, "assemble_mat: Mat sparsity differs from the plan's");
+    if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "a Mat accepts only WRITE or INC");
+    femk::AsmArgs a = base_args(plan, args);
+    form_coeffs(form->kind, &a.cstiff, &a.cmass);
+    a.coeff = need_k ? args->coeff[0]->data : args->coords->data;   // unread when cstiff == 0
+    a.row_ptr = A->sp->row_ptr;
+    a.out = A->values;
+    a.inc = acc == FEM_INC;
+    hipError_t e = femk::launch_mat(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "assemble_mat launch");
+    return FEM_OK;
+}
+
+fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                     const fem_args *args, fem_dat *b, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (form->kind != FEM_SOURCE) return fail(ctx, FEM_E_ARG, "assemble_vec needs FEM_SOURCE");
+    if ((st = check_args(ctx, form, args, true)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
+    if (!dat_ok(b, args->cell_node->to, 1)) return fail(ctx, FEM_E_ARG, "assemble_vec: b must be a Dat on the nodes");
+    if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
+    femk::AsmArgs a = base_args(plan, args);
+    a.coeff = args->coeff[0]->data;
+    a.out = b->data;
+    a.inc = acc == FEM_INC;
+    hipError_t e = femk::launch_vec(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "assemble_vec launch");
+    return FEM_OK;
+}
+
+fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                            const fem_dat *x, fem_dat *y, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (form->kind == FEM_SOURCE) return fail(ctx, FEM_E_ARG, "apply_action needs a bilinear form");
+    const bool need_k = form->kind != FEM_MASS;
+    if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
+    if (!dat_ok(x, args->cell_node->to, 1) || !dat_ok(y, args->cell_node->to, 1))
+        return fail(ctx, FEM_E_ARG, "apply_action: x and y must be Dats on the nodes");
+    if (x->data == y->data && x->set->size > 0) return fail(ctx, FEM_E_ARG, "apply_action: x and y alias");
+    if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
+    femk::AsmArgs a = base_args(plan, args);
+    form_coeffs(form->kind, &a.cstiff, &a.cmass);
+    a.coeff = need_k ? args->coeff[0]->data : args->coords->data;
+    a.x = x->data;
+    a.out = y->data;
+    a.inc = acc == FEM_INC;
+    hipError_t e = femk::launch_action(a, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "apply_action launch");
+    return FEM_OK;
+}
+
+fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args, int32_t *cell_perm,
+                        int32_t *vertex_perm, int32_t *node_perm)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if ((st = check_args(ctx, form, args, false)) != FEM_OK) return st;
+    const int dim = (int)form->cell, deg = form->degree, nl = nloc_of(dim, deg), nv = dim + 1;
+    const int64_t ncells = args->cells->size, nverts = args->cell_vertex->to->size,
+                  nnodes = args->cell_node->to->size;
+    DevBuf flag(ctx->stream);
+    HIPC(flag.alloc(sizeof(int)), "alloc");
+    if ((st = range_check(ctx, args->cell_vertex, flag.as<int>(), "cell_vertex")) != FEM_OK) return st;
+    if ((st = range_check(ctx, args->cell_node, flag.as<int>(), "cell_node")) != FEM_OK) return st;
+    std::vector<int32_t> cv(ncells * nv), cn(ncells * nl);
+    std::vector<double> X(nverts * dim);
+    hipStream_t s = ctx->stream;
+    if (!cv.empty()) HIPC(hipMemcpyAsync(cv.data(), args->cell_vertex->values, cv.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (!cn.empty()) HIPC(hipMemcpyAsync(cn.data(), args->cell_node->values, cn.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (!X.empty()) HIPC(hipMemcpyAsync(X.data(), args->coords->data, X.size() * 8, hipMemcpyDeviceToHost, s), "copy");
+    HIPC(hipStreamSynchronize(s), "sync");
+    if (cell_perm) {
+        std::vector<double> cen(ncells * dim, 0.0);
+        for (int64_t c = 0; c < ncells; ++c)
+            for (int m = 0; m < nv; ++m)
+                for (int r = 0; r < dim; ++r) cen[c * dim + r] += X[(int64_t)cv[c * nv + m] * dim + r] / nv;
+        sfc_order(cen, dim, ncells, cell_perm);
+    }
+    if (vertex_perm) sfc_order(X, dim, nverts, vertex_perm);
+    if (node_perm) {
+        std::vector<std::vector<int>> W;
+        local_weights(dim, deg, W);
+        std::vector<double> npos(nnodes * dim, 0.0);
+        std::vector<char> seen(nnodes, 0);
+        for (int64_t c = 0; c < ncells; ++c)
+            for (int l = 0; l < nl; ++l) {
+                const int32_t n = cn[c * nl + l];
+                if (seen[n]) continue;
+                seen[n] = 1;
+                for (int r = 0; r < dim; ++r) {
+                    double v = 0.0;
+                    for (int m = 0; m < nv; ++m) v += W[l][m] * X[(int64_t)cv[c * nv + m] * dim + r];
+                    npos[n * dim + r] = v / deg;
+                }
+            }
+        sfc_order(npos, dim, nnodes, node_perm);
+    }
+    return FEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal declarations of the HIP cell-loop assembler (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fem.h"
+
+struct fem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 256;
+    std::string err;
+};
+
+// Plan of the row-owned deterministic INC (see fem_plan_create in fem.h).
+struct fem_plan {
+    int is_mat = 0;              // 1: Mat plan (has gpos), 0: Dat/action plan
+    int dim = 0, degree = 0, nloc = 0;
+    int64_t ncells = 0, nrows = 0, nverts = 0;
+    int64_t nnz = 0;
+    int32_t nblk = 0;
+    int lbits = 0;               // bits of the local index in ent[]
+    int pos_bytes = 1;           // bytes per position in gpos (1 or 2)
+    int gstride = 0;             // gpos elements per entry (padded to 4 bytes)
+    int64_t cell_visits = 0;     // sum over blocks of cells gathered
+    size_t bytes = 0;            // device bytes held
+    // device arrays (owned)
+    int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
+    int32_t *blk_cptr = nullptr;  // [nblk+1] offsets into bcell
+    int32_t *bcell = nullptr;     // ascending global cell ids of each block
+    int32_t *inc_ptr = nullptr;   // [nrows+1] entry range of each row
+    uint16_t *ent = nullptr;      // [ncells*nloc] (local cell << lbits) | local index
+    void *gpos = nullptr;         // [ncells*nloc*gstride] position of each column in the row
+    // identity of what the plan was built for
+    const int32_t *cell_node = nullptr;
+    const int64_t *row_ptr = nullptr;
+};
+
+namespace femk {
+
+// ---- incidence and sparsity (fem_sparsity.hip) ----
+hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hipStream_t s);
+// Row -> incidence: ptr (int64 [nrows+1]) and ent (int32 entry ids c*nloc+l,
+// ascending within each row).  tmp must hold nrows+1 int32.
+hipError_t build_incidence(const int32_t *map, int64_t ncells, int nloc, int64_t nrows,
+                           int64_t *ptr, int32_t *ent, int32_t *tmp, hipStream_t s);
+// Unique column counts per row (count pass) or columns (fill pass).
+hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
+                       const int32_t *cmap, int nloc_c, int64_t nrows, int32_t *counts,
+                       const int64_t *row_ptr, int32_t *col_idx, int *overflow, hipStream_t s);
+hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+// gpos[e*gstride + j] = position of cmap(cell(e), j) inside row(e).
+hipError_t positions(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
+                     const int32_t *cmap, int nloc_c, int64_t nrows, const int64_t *row_ptr,
+                     const int32_t *col_idx, void *gpos, int pos_bytes, int gstride,
+                     int *missing, hipStream_t s);
+hipError_t i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
+
+// ---- assembly kernels (fem_assemble.hip) ----
+struct AsmArgs {
+    const fem_plan *plan;
+    const int32_t *cell_vertex;
+    const double *coords;
+    const int32_t *cell_node;
+    const double *coeff;     // kappa (bilinear) or f (source)
+    double cstiff, cmass;
+    const int64_t *row_ptr;
+    const double *x;         // action input
+    double *out;             // Mat values / Dat
+    int inc;                 // 1: INC, 0: WRITE
+};
+hipError_t launch_mat(const AsmArgs &a, hipStream_t s);
+hipError_t launch_vec(const AsmArgs &a, hipStream_t s);
+hipError_t launch_action(const AsmArgs &a, hipStream_t s);
+
+// Per-(dim, degree) launch limits used by the plan builder.
+struct Limits {
+    int rows_per_block;     // rows a workgroup can own
+    int slot_cap;           // Mat values a workgroup can accumulate (mat only)
+    int cell_cap;           // distinct cells per block (ent[] local-cell bits)
+};
+bool limits(int dim, int degree, bool is_mat, Limits *out);
+
+}  // namespace femk

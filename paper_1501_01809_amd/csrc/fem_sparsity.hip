@@ -1,0 +1,306 @@
+// Incidence, sparsity and position kernels of the cell-loop assembler (gfx950).
+//
+// The sparsity of a Mat assembled through a row Map and a column Map is the
+// union, over the cells incident to each row, of the cells' columns
+// (PyOP2 builds this from the pair of Maps; "Matrix arguments").  Rows are
+// processed independently: one wavefront gathers the candidate columns of a
+// row into LDS and ranks the first occurrence of each value, which yields
+// both the row's length (count pass) and its sorted unique columns (fill
+// pass) without a global sort.  Everything is deterministic: atomics are used
+// only for counting and for bucketing, and every bucket is sorted afterwards.
+#include "fem_internal.h"
+
+namespace femk {
+namespace {
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_T * SCAN_ITEMS;
+
+__global__ void k_check_range(const int32_t *__restrict__ v, int64_t n, int64_t limit,
+                              int *__restrict__ flag)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t x = v[i];
+        if (x < 0 || x >= limit) atomicOr(flag, 1);
+    }
+}
+
+__global__ void k_count(const int32_t *__restrict__ map, int64_t n, int32_t *__restrict__ cnt)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[map[i]], 1);
+}
+
+__global__ void k_fill(const int32_t *__restrict__ map, int64_t n, int32_t *__restrict__ cursor,
+                       int32_t *__restrict__ ent)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t p = atomicAdd(&cursor[map[i]], 1);
+        ent[p] = (int32_t)i;
+    }
+}
+
+// Insertion sort of each row's entry ids: makes the bucket order canonical
+// (ascending cell, then local index).
+__global__ void k_sort_rows(const int64_t *__restrict__ ptr, int32_t *__restrict__ ent, int64_t nrows)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t a = ptr[r], b = ptr[r + 1];
+        for (int64_t i = a + 1; i < b; ++i) {
+            int32_t key = ent[i];
+            int64_t j = i - 1;
+            while (j >= a && ent[j] > key) { ent[j + 1] = ent[j]; --j; }
+            ent[j + 1] = key;
+        }
+    }
+}
+
+__global__ void k_i64_to_i32(const int64_t *__restrict__ in, int32_t *__restrict__ out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)in[i];
+}
+
+// Block-wide exclusive scan of one int64 per thread (Hillis-Steele in LDS).
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t *total)
+{
+    __shared__ int64_t s[SCAN_T];
+    const int t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int64_t add = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    int64_t incl = s[t];
+    *total = s[SCAN_T - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tiles(const int32_t *__restrict__ in, int64_t n,
+                                                       int64_t *__restrict__ tile_sum)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int64_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int64_t *__restrict__ tile_sum, int64_t ntiles,
+                                                      int64_t *__restrict__ out_total)
+{
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += SCAN_T) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < ntiles ? tile_sum[i] : 0;
+        int64_t tot;
+        int64_t ex = block_exclusive_scan(v, &tot);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *out_total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int32_t *__restrict__ in, int64_t n,
+                                                       const int64_t *__restrict__ tile_sum,
+                                                       int64_t *__restrict__ out)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(s, &tot) + tile_sum[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+}
+
+constexpr int RC_CAP = 2048;   // candidate columns of one row held in LDS
+
+// One 64-lane workgroup per row (grid-stride).  Candidates = columns of every
+// incident cell; a candidate is "first" if no equal value precedes it; the
+// rank of a first candidate among first candidates with smaller value is its
+// position in the sorted unique row.
+__global__ __launch_bounds__(64) void k_row_columns(
+    const int64_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_ent, int nloc_r,
+    const int32_t *__restrict__ cmap, int nloc_c, int64_t nrows, int32_t *__restrict__ counts,
+    const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx, int *__restrict__ overflow)
+{
+    __shared__ int32_t cand[RC_CAP];
+    __shared__ uint8_t first[RC_CAP];
+    const int t0 = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t e0 = inc_ptr[r], e1 = inc_ptr[r + 1];
+        const int64_t n64 = (e1 - e0) * nloc_c;
+        if (n64 > RC_CAP) {
+            if (t0 == 0) atomicOr(overflow, 1);
+            continue;
+        }
+        const int n = (int)n64;
+        for (int t = t0; t < n; t += 64) {
+            int64_t e = inc_ent[e0 + t / nloc_c];
+            int64_t c = e / nloc_r;
+            cand[t] = cmap[c * nloc_c + t % nloc_c];
+        }
+        __syncthreads();
+        int mine = 0;
+        for (int t = t0; t < n; t += 64) {
+            const int32_t v = cand[t];
+            uint8_t f = 1;
+            for (int u = 0; u < t; ++u)
+                if (cand[u] == v) { f = 0; break; }
+            first[t] = f;
+            mine += f;
+        }
+        __syncthreads();
+        if (!col_idx) {
+            for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+            if (t0 == 0) counts[r] = mine;
+        } else {
+            const int64_t base = row_ptr[r];
+            for (int t = t0; t < n; t += 64) {
+                if (!first[t]) continue;
+                const int32_t v = cand[t];
+                int rank = 0;
+                for (int u = 0; u < n; ++u) rank += (first[u] && cand[u] < v);
+                col_idx[base + rank] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename PosT>
+__global__ void k_positions(const int64_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_ent,
+                            int nloc_r, const int32_t *__restrict__ cmap, int nloc_c, int64_t nrows,
+                            const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                            PosT *__restrict__ gpos, int gstride, int *__restrict__ missing)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = row_ptr[r], len = row_ptr[r + 1] - a;
+        for (int64_t k = inc_ptr[r]; k < inc_ptr[r + 1]; ++k) {
+            const int64_t c = inc_ent[k] / nloc_r;
+            for (int j = 0; j < nloc_c; ++j) {
+                const int32_t v = cmap[c * nloc_c + j];
+                int64_t lo = 0, hi = len - 1, at = -1;
+                while (lo <= hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    int32_t w = col_idx[a + mid];
+                    if (w == v) { at = mid; break; }
+                    if (w < v) lo = mid + 1; else hi = mid - 1;
+                }
+                if (at < 0) { atomicOr(missing, 1); at = 0; }
+                gpos[k * gstride + j] = (PosT)at;
+            }
+        }
+    }
+}
+
+inline int grid_for(int64_t n, int threads)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_range, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n, limit, flag);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s)
+{
+    const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *tile_sum = nullptr;
+    hipError_t e = hipMallocAsync((void **)&tile_sum, sizeof(int64_t) * (ntiles + 1), s);
+    if (e != hipSuccess) return e;
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_T), 0, s, in, n, tile_sum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, tile_sum, ntiles, out + n);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(SCAN_T), 0, s, in, n, tile_sum, out);
+    e = hipGetLastError();
+    hipError_t e2 = hipFreeAsync(tile_sum, s);
+    return e != hipSuccess ? e : e2;
+}
+
+hipError_t build_incidence(const int32_t *map, int64_t ncells, int nloc, int64_t nrows,
+                           int64_t *ptr, int32_t *ent, int32_t *tmp, hipStream_t s)
+{
+    const int64_t n = ncells * nloc;
+    hipError_t e = hipMemsetAsync(tmp, 0, sizeof(int32_t) * (nrows + 1), s);
+    if (e != hipSuccess) return e;
+    if (n > 0) hipLaunchKernelGGL(k_count, dim3(grid_for(n, 256)), dim3(256), 0, s, map, n, tmp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = exclusive_scan(tmp, ptr, nrows, s)) != hipSuccess) return e;
+    if (nrows > 0)
+        hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(nrows, 256)), dim3(256), 0, s, ptr, tmp, nrows);
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, map, n, tmp, ent);
+    if (nrows > 0)
+        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(nrows, 128)), dim3(128), 0, s, ptr, ent, nrows);
+    return hipGetLastError();
+}
+
+hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
+                       const int32_t *cmap, int nloc_c, int64_t nrows, int32_t *counts,
+                       const int64_t *row_ptr, int32_t *col_idx, int *overflow, hipStream_t s)
+{
+    if (nrows <= 0) return hipSuccess;
+    int64_t g = nrows < 32768 ? nrows : 32768;
+    hipLaunchKernelGGL(k_row_columns, dim3((unsigned)g), dim3(64), 0, s, inc_ptr, inc_ent, nloc_r,
+                       cmap, nloc_c, nrows, counts, row_ptr, col_idx, overflow);
+    return hipGetLastError();
+}
+
+hipError_t positions(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
+                     const int32_t *cmap, int nloc_c, int64_t nrows, const int64_t *row_ptr,
+                     const int32_t *col_idx, void *gpos, int pos_bytes, int gstride,
+                     int *missing, hipStream_t s)
+{
+    if (nrows <= 0) return hipSuccess;
+    if (pos_bytes == 1)
+        hipLaunchKernelGGL(k_positions<uint8_t>, dim3(grid_for(nrows, 128)), dim3(128), 0, s, inc_ptr,
+                           inc_ent, nloc_r, cmap, nloc_c, nrows, row_ptr, col_idx, (uint8_t *)gpos,
+                           gstride, missing);
+    else
+        hipLaunchKernelGGL(k_positions<uint16_t>, dim3(grid_for(nrows, 128)), dim3(128), 0, s, inc_ptr,
+                           inc_ent, nloc_r, cmap, nloc_c, nrows, row_ptr, col_idx, (uint16_t *)gpos,
+                           gstride, missing);
+    return hipGetLastError();
+}
+
+hipError_t i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace femk

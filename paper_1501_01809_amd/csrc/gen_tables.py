@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Generate ``fem_tables.h``: exact reference integrals of the Lagrange P1-P3
+bases on triangles and tetrahedra, emitted as straight-line FP64 device code.
+
+The element tensors of the local kernels are written in "metric" form
+(the reference-tensor idea the paper cites for FFC: a per-cell geometry
+tensor contracted with a cell-independent reference tensor):
+
+  A_ij = sum_k sum_{m<=n} P[k][mn] W[k][mn][i][j]  +  madet * Mref_ij
+  P[k][mn] = cstiff * kappa_k * |det J| grad(l_m).grad(l_n)
+  W[k][mn][i][j] = int_ref l_k (d_m phi_i d_n phi_j + [m!=n] d_n phi_i d_m phi_j)
+  Mref_ij = int_ref phi_i phi_j,   madet = cmass * |det J|
+  b_i = |det J| sum_k f_k int_ref l_k phi_i
+
+with l_0..l_d the barycentric coordinates and d_m the derivative with respect
+to l_m (chain rule: grad phi = sum_m d_m phi grad l_m).  All integrals are
+exact rationals (int_ref l^a = a!/(|a|+d)!), rounded once to double and
+printed as hexadecimal literals; zero terms are dropped at generation time.
+
+Local node order: vertices; edges (a<b lexicographic), the two P3 edge nodes
+ordered from a; P3 tetrahedron faces (a<b<c lexicographic) or the P3
+triangle's interior node.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+import sys
+from fractions import Fraction
+from math import factorial
+
+
+def poly_mul(p, q):
+    out = {}
+    for a, ca in p.items():
+        for b, cb in q.items():
+            e = tuple(x + y for x, y in zip(a, b))
+            out[e] = out.get(e, 0) + ca * cb
+    return {k: v for k, v in out.items() if v != 0}
+
+
+def poly_add(*ps):
+    out = {}
+    for p in ps:
+        for a, c in p.items():
+            out[a] = out.get(a, 0) + c
+    return {k: v for k, v in out.items() if v != 0}
+
+
+def poly_scale(p, s):
+    return {a: c * s for a, c in p.items()}
+
+
+def poly_d(p, m):
+    out = {}
+    for a, c in p.items():
+        if a[m]:
+            e = list(a); e[m] -= 1
+            out[tuple(e)] = out.get(tuple(e), 0) + c * a[m]
+    return out
+
+
+def integrate(p, d):
+    s = Fraction(0)
+    for a, c in p.items():
+        num = 1
+        for x in a:
+            num *= factorial(x)
+        s += c * Fraction(num, factorial(sum(a) + d))
+    return s
+
+
+def lam(nv, m):
+    e = [0] * nv; e[m] = 1
+    return {tuple(e): Fraction(1)}
+
+
+def const(nv, c):
+    return {tuple([0] * nv): Fraction(c)}
+
+
+def basis(d, k):
+    """Lagrange basis as polynomials in the barycentrics l_0..l_d."""
+    nv = d + 1
+    L = [lam(nv, m) for m in range(nv)]
+    B = []
+    for i in range(nv):
+        if k == 1:
+            B.append(L[i])
+        elif k == 2:   # l (2l - 1)
+            B.append(poly_mul(L[i], poly_add(poly_scale(L[i], 2), const(nv, -1))))
+        else:          # l (3l - 1)(3l - 2) / 2
+            B.append(poly_scale(poly_mul(L[i], poly_mul(poly_add(poly_scale(L[i], 3), const(nv, -1)),
+                                                         poly_add(poly_scale(L[i], 3), const(nv, -2)))),
+                                Fraction(1, 2)))
+    for a, b in itertools.combinations(range(nv), 2):
+        if k == 2:
+            B.append(poly_scale(poly_mul(L[a], L[b]), 4))
+        elif k == 3:
+            ab = poly_mul(L[a], L[b])
+            B.append(poly_scale(poly_mul(ab, poly_add(poly_scale(L[a], 3), const(nv, -1))), Fraction(9, 2)))
+            B.append(poly_scale(poly_mul(ab, poly_add(poly_scale(L[b], 3), const(nv, -1))), Fraction(9, 2)))
+    if k == 3:
+        for f in itertools.combinations(range(nv), 3):
+            p = const(nv, 27)
+            for a in f:
+                p = poly_mul(p, L[a])
+            B.append(p)
+    return B
+
+
+def hexlit(x: Fraction) -> str:
+    v = float(x)
+    if v == 0.0:
+        return "0.0"
+    return v.hex()
+
+
+def metric_pairs(nv):
+    return [(m, n) for m in range(nv) for n in range(m, nv)]
+
+
+def tables(d, k):
+    nv = d + 1
+    B = basis(d, k)
+    n = len(B)
+    dB = [[poly_d(B[i], m) for m in range(nv)] for i in range(n)]
+    pairs = metric_pairs(nv)
+    # stiffness terms for each upper entry (i<=j): list of (k, mn, coef)
+    stiff = {}
+    for i in range(n):
+        for j in range(i, n):
+            terms = []
+            for kk in range(nv):
+                for t, (m, q) in enumerate(pairs):
+                    w = integrate(poly_mul(lam(nv, kk), poly_mul(dB[i][m], dB[j][q])), d)
+                    if m != q:
+                        w += integrate(poly_mul(lam(nv, kk), poly_mul(dB[i][q], dB[j][m])), d)
+                    if w != 0:
+                        terms.append((kk, t, w))
+            stiff[(i, j)] = terms
+    mass = {(i, j): integrate(poly_mul(B[i], B[j]), d) for i in range(n) for j in range(i, n)}
+    src = [[integrate(poly_mul(lam(nv, kk), B[i]), d) for kk in range(nv)] for i in range(n)]
+    return n, pairs, stiff, mass, src
+
+
+def entry_expr(i, j, NM, stiff, mass):
+    lines = []
+    first = True
+    for (kk, t, w) in stiff[(i, j)]:
+        idx = kk * NM + t
+        if first:
+            lines.append(f"double e = {hexlit(w)} * P[{idx}];")
+            first = False
+        else:
+            lines.append(f"e = __builtin_fma({hexlit(w)}, P[{idx}], e);")
+    mw = mass[(i, j)]
+    if mw != 0:
+        if first:
+            lines.append(f"double e = {hexlit(mw)} * madet;")
+            first = False
+        else:
+            lines.append(f"e = __builtin_fma({hexlit(mw)}, madet, e);")
+    if first:
+        lines.append("double e = 0.0;")
+    return lines
+
+
+def split_groups(entries, cost, G):
+    """Greedy longest-processing-time partition of entries into G groups."""
+    groups = [[] for _ in range(G)]
+    load = [0] * G
+    for e in sorted(entries, key=lambda e: -cost[e]):
+        g = min(range(G), key=lambda g: load[g])
+        groups[g].append(e); load[g] += cost[e]
+    return [sorted(g) for g in groups], load
+
+
+def emit(d, k, G):
+    n, pairs, stiff, mass, src = tables(d, k)
+    nv = d + 1
+    NM = len(pairs)
+    NE = n * (n + 1) // 2
+    name = f"Tab{d}{k}"
+    out = []
+    out.append(f"struct {name} {{")
+    out.append(f"  static constexpr int DIM = {d}, DEG = {k}, NLOC = {n}, NV = {nv}, NM = {NM}, NE = {NE}, NG = {G};")
+    nterms = sum(len(v) for v in stiff.values()) + sum(1 for v in mass.values() if v != 0)
+    out.append(f"  static constexpr int TERMS = {nterms};")
+    entries = sorted(stiff)
+    cost = {e: len(stiff[e]) + (1 if mass[e] != 0 else 0) for e in entries}
+    groups, load = split_groups(entries, cost, G)
+    out.append(f"  // entry-group loads (terms): {load}")
+    for g, grp in enumerate(groups):
+        out.append(f"  __device__ __forceinline__ static void mat_group{g}(const double* __restrict__ P, double madet, double* __restrict__ E) {{")
+        for (i, j) in grp:
+            out.append("    {")
+            for l in entry_expr(i, j, NM, stiff, mass):
+                out.append("      " + l)
+            out.append(f"      E[{i * n + j}] = e;" + (f" E[{j * n + i}] = e;" if i != j else ""))
+            out.append("    }")
+        out.append("  }")
+    out.append("  // upper triangle, row-major (i<=j), Eu[NE]")
+    out.append("  __device__ __forceinline__ static void mat_upper(const double* __restrict__ P, double madet, double* __restrict__ Eu) {")
+    u = 0
+    for i in range(n):
+        for j in range(i, n):
+            out.append("    {")
+            for l in entry_expr(i, j, NM, stiff, mass):
+                out.append("      " + l)
+            out.append(f"      Eu[{u}] = e;")
+            out.append("    }")
+            u += 1
+    out.append("  }")
+    out.append("  // y += A x for one cell, entries consumed as soon as they are formed")
+    out.append("  __device__ __forceinline__ static void act(const double* __restrict__ P, double madet, const double* __restrict__ x, double* __restrict__ y) {")
+    for i in range(n):
+        for j in range(i, n):
+            out.append("    {")
+            for l in entry_expr(i, j, NM, stiff, mass):
+                out.append("      " + l)
+            out.append(f"      y[{i}] = __builtin_fma(e, x[{j}], y[{i}]);" + (f" y[{j}] = __builtin_fma(e, x[{i}], y[{j}]);" if i != j else ""))
+            out.append("    }")
+    out.append("  }")
+    out.append("  // b_i = adet * sum_k f_k int l_k phi_i")
+    out.append("  __device__ __forceinline__ static void vec(const double* __restrict__ f, double adet, double* __restrict__ b) {")
+    for i in range(n):
+        terms = [(kk, src[i][kk]) for kk in range(nv) if src[i][kk] != 0]
+        expr = None
+        for kk, w in terms:
+            expr = f"{hexlit(w)} * f[{kk}]" if expr is None else f"__builtin_fma({hexlit(w)}, f[{kk}], {expr})"
+        out.append(f"    b[{i}] = adet * ({expr if expr else '0.0'});")
+    out.append("  }")
+    out.append("};")
+    return "\n".join(out), nterms
+
+
+def main(path):
+    parts = ["// Generated by gen_tables.py -- exact reference integrals of Lagrange P1-P3",
+             "// bases (see the generator's docstring for the formulas).  Do not edit.",
+             "#pragma once", "namespace femtab {"]
+    summary = []
+    for d in (2, 3):
+        for k in (1, 2, 3):
+            G = 1 if k == 1 else 4
+            code, nt = emit(d, k, G)
+            parts.append(code)
+            summary.append((d, k, nt))
+    parts.append("}  // namespace femtab")
+    txt = "\n".join(parts) + "\n"
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        fh.write(txt)
+    os.replace(tmp, path)
+    return summary
+
+
+if __name__ == "__main__":
+    out = sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "fem_tables.h")
+    for d, k, nt in main(out):
+        print(f"dim {d} degree {k}: {nt} terms")

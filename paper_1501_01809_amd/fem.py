@@ -1,0 +1,255 @@
+"""Thin ctypes binding of ``libfem.so`` (include/fem.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.
+Function names are the C ABI's names.  Importing this module never falls back
+to anything: if the HIP library is missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfem.so")
+
+FEM_OK, FEM_E_ARG, FEM_E_RANGE, FEM_E_OVERFLOW, FEM_E_UNSUPPORTED, FEM_E_NOMEM, FEM_E_DEVICE = range(7)
+STATUS_NAMES = {0: "FEM_OK", 1: "FEM_E_ARG", 2: "FEM_E_RANGE", 3: "FEM_E_OVERFLOW",
+                4: "FEM_E_UNSUPPORTED", 5: "FEM_E_NOMEM", 6: "FEM_E_DEVICE"}
+FEM_READ, FEM_WRITE, FEM_INC = 0, 1, 2
+FEM_TRIANGLE, FEM_TETRAHEDRON = 2, 3
+FEM_FP64, FEM_FP32, FEM_BF16, FEM_FP16 = 0, 1, 2, 3
+FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE = 0, 1, 2, 3
+
+KINDS = {"mass": FEM_MASS, "laplace": FEM_LAPLACE, "helmholtz": FEM_HELMHOLTZ, "source": FEM_SOURCE}
+
+
+class FemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fem_set(C.Structure):
+    _fields_ = [("size", C.c_int64)]
+
+
+class fem_map(C.Structure):
+    _fields_ = [("from_", C.POINTER(fem_set)), ("to", C.POINTER(fem_set)),
+                ("arity", C.c_int32), ("values", C.c_void_p)]
+
+
+class fem_dat(C.Structure):
+    _fields_ = [("set", C.POINTER(fem_set)), ("dim", C.c_int32), ("data", C.c_void_p)]
+
+
+class fem_sparsity(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p)]
+
+
+class fem_mat(C.Structure):
+    _fields_ = [("sp", C.POINTER(fem_sparsity)), ("values", C.c_void_p)]
+
+
+class fem_form(C.Structure):
+    _fields_ = [("kind", C.c_int), ("cell", C.c_int), ("degree", C.c_int32),
+                ("dim", C.c_int32), ("prec", C.c_int)]
+
+
+class fem_args(C.Structure):
+    _fields_ = [("cells", C.POINTER(fem_set)), ("cell_vertex", C.POINTER(fem_map)),
+                ("coords", C.POINTER(fem_dat)), ("cell_node", C.POINTER(fem_map)),
+                ("coeff", C.POINTER(fem_dat) * 4), ("ncoeff", C.c_int32)]
+
+
+EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_error", "fem_sync",
+           "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
+           "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
+           "fem_renumber"]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.fem_ctx_create.argtypes = [C.c_int, P, C.POINTER(P)]
+        L.fem_ctx_destroy.argtypes = [P]; L.fem_ctx_destroy.restype = None
+        L.fem_ctx_set_stream.argtypes = [P, P]
+        L.fem_last_error.argtypes = [P]; L.fem_last_error.restype = C.c_char_p
+        L.fem_sync.argtypes = [P]
+        L.fem_build_sparsity.argtypes = [P, C.POINTER(fem_map), C.POINTER(fem_map), C.POINTER(fem_sparsity)]
+        L.fem_plan_create.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_sparsity),
+                                      C.POINTER(P)]
+        L.fem_plan_destroy.argtypes = [P]; L.fem_plan_destroy.restype = None
+        L.fem_plan_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.fem_par_loop_assemble_mat.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args),
+                                                C.POINTER(fem_mat), C.c_int]
+        L.fem_par_loop_assemble_vec.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args),
+                                                C.POINTER(fem_dat), C.c_int]
+        L.fem_apply_action.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_dat),
+                                       C.POINTER(fem_dat), C.c_int]
+        L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
+        for name in EXPORTS:
+            if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+class Context:
+    """fem_ctx bound to a device and to torch's current stream on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.h = C.c_void_p()
+        st = L.fem_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(self.h))
+        if st != FEM_OK:
+            raise FemError(st, "fem_ctx_create failed")
+
+    def check(self, st):
+        if st != FEM_OK:
+            raise FemError(st, lib().fem_last_error(self.h).decode())
+
+    def set_stream(self, stream):
+        self.check(lib().fem_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self.h:
+            lib().fem_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def form(kind="helmholtz", cell=3, degree=1, dim=1, prec=FEM_FP64):
+    return fem_form(KINDS.get(kind, kind) if isinstance(kind, str) else kind, cell, degree, dim, prec)
+
+
+class Args:
+    """par_loop arguments over torch device tensors (references kept alive)."""
+
+    def __init__(self, cell_vertex, coords, cell_node, nnodes, coeffs=()):
+        import torch
+        assert cell_vertex.dtype == torch.int32 and cell_node.dtype == torch.int32
+        assert coords.dtype == torch.float64
+        self.cell_vertex, self.coords, self.cell_node = cell_vertex, coords, cell_node
+        self.coeffs = list(coeffs)
+        self.cells = fem_set(cell_vertex.shape[0])
+        self.verts = fem_set(coords.shape[0])
+        self.nodes = fem_set(nnodes)
+        self.cv = fem_map(C.pointer(self.cells), C.pointer(self.verts), cell_vertex.shape[1], _ptr(cell_vertex))
+        self.cn = fem_map(C.pointer(self.cells), C.pointer(self.nodes), cell_node.shape[1], _ptr(cell_node))
+        self.X = fem_dat(C.pointer(self.verts), coords.shape[1], _ptr(coords))
+        self.cdats = [fem_dat(C.pointer(self.verts), 1, _ptr(c)) for c in self.coeffs]
+        self.c = fem_args()
+        self.c.cells = C.pointer(self.cells)
+        self.c.cell_vertex = C.pointer(self.cv)
+        self.c.coords = C.pointer(self.X)
+        self.c.cell_node = C.pointer(self.cn)
+        for i, d in enumerate(self.cdats):
+            self.c.coeff[i] = C.pointer(d)
+        self.c.ncoeff = len(self.cdats)
+
+    def with_coeffs(self, *coeffs):
+        return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs)
+
+
+class Sparsity:
+    def __init__(self, row_ptr, col_idx, nrows, ncols):
+        self.row_ptr, self.col_idx = row_ptr, col_idx
+        self.c = fem_sparsity(nrows, ncols, int(col_idx.numel()), _ptr(row_ptr), _ptr(col_idx))
+
+
+class Plan:
+    def __init__(self, h, keep):
+        self.h, self._keep = h, keep
+
+    def info(self):
+        nb, cv, by = C.c_int64(), C.c_int64(), C.c_int64()
+        lib().fem_plan_info(self.h, C.byref(nb), C.byref(cv), C.byref(by))
+        return {"blocks": nb.value, "cell_visits": cv.value, "device_bytes": by.value}
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().fem_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | None = None) -> Sparsity:
+    """Two-pass CSR sparsity (count, then fill) of the Mat through rmap/cmap."""
+    import torch
+    cmap = rmap if cmap is None else cmap
+    ncols = nrows if ncols is None else ncols
+    cells = fem_set(rmap.shape[0]); rs = fem_set(nrows); cs = fem_set(ncols)
+    rm = fem_map(C.pointer(cells), C.pointer(rs), rmap.shape[1], _ptr(rmap))
+    cm = fem_map(C.pointer(cells), C.pointer(cs), cmap.shape[1], _ptr(cmap))
+    row_ptr = torch.empty(nrows + 1, dtype=torch.int64, device=rmap.device)
+    sp = fem_sparsity(0, 0, 0, _ptr(row_ptr), None)
+    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp)))
+    col_idx = torch.empty(max(sp.nnz, 1), dtype=torch.int32, device=rmap.device)
+    sp.col_idx = C.c_void_p(col_idx.data_ptr())
+    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp)))
+    return Sparsity(row_ptr, col_idx[:sp.nnz], nrows, ncols)
+
+
+def fem_plan_create(ctx: Context, frm: fem_form, args: Args, sp: Sparsity | None = None) -> Plan:
+    h = C.c_void_p()
+    ctx.check(lib().fem_plan_create(ctx.h, C.byref(frm), C.byref(args.c),
+                                    C.byref(sp.c) if sp is not None else None, C.byref(h)))
+    return Plan(h, (args, sp))
+
+
+def fem_par_loop_assemble_mat(ctx: Context, plan: Plan, frm: fem_form, args: Args, values, sp: Sparsity,
+                              acc: int = FEM_WRITE):
+    m = fem_mat(C.pointer(sp.c), _ptr(values))
+    ctx.check(lib().fem_par_loop_assemble_mat(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(m), acc))
+
+
+def fem_par_loop_assemble_vec(ctx: Context, plan: Plan, frm: fem_form, args: Args, b, acc: int = FEM_WRITE):
+    d = fem_dat(C.pointer(args.nodes), 1, _ptr(b))
+    ctx.check(lib().fem_par_loop_assemble_vec(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(d), acc))
+
+
+def fem_apply_action(ctx: Context, plan: Plan, frm: fem_form, args: Args, x, y, acc: int = FEM_WRITE):
+    dx = fem_dat(C.pointer(args.nodes), 1, _ptr(x))
+    dy = fem_dat(C.pointer(args.nodes), 1, _ptr(y))
+    ctx.check(lib().fem_apply_action(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(dx),
+                                     C.byref(dy), acc))
+
+
+def fem_renumber(ctx: Context, frm: fem_form, args: Args):
+    """(cell_perm, vertex_perm, node_perm) as numpy int32: new -> old."""
+    cp = np.empty(args.cells.size, dtype=np.int32)
+    vp = np.empty(args.verts.size, dtype=np.int32)
+    npm = np.empty(args.nodes.size, dtype=np.int32)
+    ctx.check(lib().fem_renumber(ctx.h, C.byref(frm), C.byref(args.c), cp.ctypes.data_as(C.c_void_p),
+                                 vp.ctypes.data_as(C.c_void_p), npm.ctypes.data_as(C.c_void_p)))
+    return cp, vp, npm
+
+
+def fem_sync(ctx: Context):
+    ctx.check(lib().fem_sync(ctx.h))
