@@ -49,8 +49,8 @@ def lib():
         L.oracle_simplex_rule.argtypes = [I, I, P, P]; L.oracle_simplex_rule.restype = I
         L.oracle_nloc.argtypes = [I, I]; L.oracle_nloc.restype = I
         L.oracle_basis.argtypes = [I, I, P, P, P]; L.oracle_basis.restype = None
-        L.oracle_element_matrix.argtypes = [I, I, P, P, D, D, P]; L.oracle_element_matrix.restype = I
-        L.oracle_element_vector.argtypes = [I, I, P, P, P]; L.oracle_element_vector.restype = I
+        L.oracle_element_matrix.argtypes = [I, I, P, P, D, D, P, P]; L.oracle_element_matrix.restype = I
+        L.oracle_element_vector.argtypes = [I, I, P, P, P, P]; L.oracle_element_vector.restype = I
         L.oracle_sparsity.argtypes = [L64, I, P, I, P, L64, L64, P, P]; L.oracle_sparsity.restype = L64
         L.oracle_assemble_mat.argtypes = [I, I, L64, P, P, P, P, D, D, P, P, L64, P, P]
         L.oracle_assemble_mat.restype = I
@@ -110,7 +110,7 @@ def element_matrix(dim, degree, xv, kv, form="helmholtz"):
     cs, cm = FORMS[form]
     xv = _c(xv, np.float64); kv = _c(kv, np.float64)
     n = nloc(dim, degree); A = np.zeros((n, n))
-    if lib().oracle_element_matrix(dim, degree, _p(xv), _p(kv), cs, cm, _p(A)):
+    if lib().oracle_element_matrix(dim, degree, _p(xv), _p(kv), cs, cm, _p(A), None):
         raise RuntimeError("element_matrix failed")
     return A
 
@@ -118,7 +118,7 @@ def element_matrix(dim, degree, xv, kv, form="helmholtz"):
 def element_vector(dim, degree, xv, fv):
     xv = _c(xv, np.float64); fv = _c(fv, np.float64)
     n = nloc(dim, degree); b = np.zeros(n)
-    if lib().oracle_element_vector(dim, degree, _p(xv), _p(fv), _p(b)):
+    if lib().oracle_element_vector(dim, degree, _p(xv), _p(fv), _p(b), None):
         raise RuntimeError("element_vector failed")
     return b
 

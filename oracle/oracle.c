@@ -308,7 +308,7 @@ static void eval_at_point(int dim, int degree, const double *xv, const double *J
  * kv: kappa at the vertices [dim+1].
  */
 int oracle_element_matrix(int dim, int degree, const double *xv, const double *kv,
-                          double cstiff, double cmass, double *A)
+                          double cstiff, double cmass, double *A, double *Aabs)
 {
     const int n = oracle_nloc(dim, degree), nv = dim + 1;
     if (n < 0) return -1;
@@ -318,6 +318,7 @@ int oracle_element_matrix(int dim, int degree, const double *xv, const double *k
     double det = cell_geometry(dim, xv, J, Jinv);
     double adet = fabs(det);
     memset(A, 0, sizeof(double) * n * n);
+    if (Aabs) memset(Aabs, 0, sizeof(double) * n * n);
     for (int p = 0; p < R.np; ++p) {
         double lam[4], phi[MAXLOC], gphi[MAXLOC * 3];
         eval_at_point(dim, degree, xv, Jinv, &R.pts[p * dim], lam, phi, gphi);
@@ -326,16 +327,23 @@ int oracle_element_matrix(int dim, int degree, const double *xv, const double *k
         double w = R.wts[p] * adet;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
-                double g = 0.0;
-                for (int r = 0; r < dim; ++r) g += gphi[i * dim + r] * gphi[j * dim + r];
+                double g = 0.0, ga = 0.0;
+                for (int r = 0; r < dim; ++r) {
+                    g += gphi[i * dim + r] * gphi[j * dim + r];
+                    ga += fabs(gphi[i * dim + r] * gphi[j * dim + r]);
+                }
                 A[i * n + j] += w * (cstiff * kap * g + cmass * phi[i] * phi[j]);
+                /* magnitude of the summed terms: the scale of the rounding
+                 * error of this entry (sum of |terms| bounds it) */
+                if (Aabs) Aabs[i * n + j] += fabs(w) * (fabs(cstiff * kap) * ga + fabs(cmass * phi[i] * phi[j]));
             }
     }
     return 0;
 }
 
 /* Element vector of  f v  with f a P1 field (fv: f at the vertices). */
-int oracle_element_vector(int dim, int degree, const double *xv, const double *fv, double *b)
+int oracle_element_vector(int dim, int degree, const double *xv, const double *fv, double *b,
+                          double *babs)
 {
     const int n = oracle_nloc(dim, degree), nv = dim + 1;
     if (n < 0) return -1;
@@ -344,12 +352,16 @@ int oracle_element_vector(int dim, int degree, const double *xv, const double *f
     double J[9], Jinv[9];
     double adet = fabs(cell_geometry(dim, xv, J, Jinv));
     memset(b, 0, sizeof(double) * n);
+    if (babs) memset(babs, 0, sizeof(double) * n);
     for (int p = 0; p < R.np; ++p) {
         double lam[4], phi[MAXLOC], gphi[MAXLOC * 3];
         eval_at_point(dim, degree, xv, Jinv, &R.pts[p * dim], lam, phi, gphi);
-        double fx = 0.0;
-        for (int m = 0; m < nv; ++m) fx += fv[m] * lam[m];
-        for (int i = 0; i < n; ++i) b[i] += R.wts[p] * adet * fx * phi[i];
+        double fx = 0.0, fa = 0.0;
+        for (int m = 0; m < nv; ++m) { fx += fv[m] * lam[m]; fa += fabs(fv[m] * lam[m]); }
+        for (int i = 0; i < n; ++i) {
+            b[i] += R.wts[p] * adet * fx * phi[i];
+            if (babs) babs[i] += fabs(R.wts[p] * adet * phi[i]) * fa;
+        }
     }
     return 0;
 }
@@ -459,7 +471,8 @@ static int64_t find_col(const int64_t *row_ptr, const int32_t *col_idx, int64_t 
 /*
  * values[k] (k indexes the CSR given by row_ptr/col_idx, which must contain
  * the assembled pattern) is overwritten with the assembled matrix; absval[k]
- * (optional) with the sum of |contribution|.  Returns 0, or -3 if a
+ * (optional) with the magnitude scale of the rounding error: the sum over
+ * cells and quadrature points of |weight * integrand term|.  Returns 0, or -3 if a
  * contribution falls outside the pattern.
  */
 int oracle_assemble_mat(int dim, int degree, int64_t ncells, const int32_t *cell_vertex,
@@ -472,17 +485,17 @@ int oracle_assemble_mat(int dim, int degree, int64_t ncells, const int32_t *cell
     int64_t nnz = row_ptr[nrows];
     memset(values, 0, sizeof(double) * (size_t)nnz);
     if (absval) memset(absval, 0, sizeof(double) * (size_t)nnz);
-    double xv[12], kv[4], A[MAXLOC * MAXLOC];
+    double xv[12], kv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC];
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, kappa, xv, kv);
-        if (oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A)) return -1;
+        if (oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A, Aa)) return -1;
         for (int i = 0; i < n; ++i) {
             int32_t r = cell_node[c * n + i];
             for (int j = 0; j < n; ++j) {
                 int64_t k = find_col(row_ptr, col_idx, r, cell_node[c * n + j]);
                 if (k < 0) return -3;
                 values[k] += A[i * n + j];
-                if (absval) absval[k] += fabs(A[i * n + j]);
+                if (absval) absval[k] += Aa[i * n + j];
             }
         }
     }
@@ -498,15 +511,15 @@ int oracle_assemble_vec(int dim, int degree, int64_t ncells, const int32_t *cell
     if (n < 0) return -1;
     memset(b, 0, sizeof(double) * (size_t)nrows);
     if (absb) memset(absb, 0, sizeof(double) * (size_t)nrows);
-    double xv[12], fv[4], be[MAXLOC];
+    double xv[12], fv[4], be[MAXLOC], ba[MAXLOC];
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, f, xv, fv);
-        if (oracle_element_vector(dim, degree, xv, fv, be)) return -1;
+        if (oracle_element_vector(dim, degree, xv, fv, be, ba)) return -1;
         for (int i = 0; i < n; ++i) {
             int32_t r = cell_node[c * n + i];
             if (r < 0 || r >= nrows) return -2;
             b[r] += be[i];
-            if (absb) absb[r] += fabs(be[i]);
+            if (absb) absb[r] += ba[i];
         }
     }
     return 0;
@@ -522,17 +535,18 @@ int oracle_apply_action(int dim, int degree, int64_t ncells, const int32_t *cell
     if (n < 0) return -1;
     memset(y, 0, sizeof(double) * (size_t)nrows);
     if (absy) memset(absy, 0, sizeof(double) * (size_t)nrows);
-    double xv[12], kv[4], A[MAXLOC * MAXLOC];
+    double xv[12], kv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC];
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, kappa, xv, kv);
-        if (oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A)) return -1;
+        if (oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A, Aa)) return -1;
         for (int i = 0; i < n; ++i) {
             int32_t r = cell_node[c * n + i];
             if (r < 0 || r >= nrows) return -2;
             double s = 0.0, sa = 0.0;
             for (int j = 0; j < n; ++j) {
-                double t = A[i * n + j] * x[cell_node[c * n + j]];
-                s += t; sa += fabs(t);
+                double xj = x[cell_node[c * n + j]];
+                s += A[i * n + j] * xj;
+                sa += Aa[i * n + j] * fabs(xj);
             }
             y[r] += s;
             if (absy) absy[r] += sa;
@@ -567,14 +581,14 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
     if (!slot || !cols || !vals || !abss || !cnt) { free(slot); free(cols); free(vals); free(abss); free(cnt); return -1; }
     for (int64_t r = 0; r < nrows; ++r) slot[r] = -1;
     for (int64_t s = 0; s < nsel; ++s) slot[rows[s]] = s;
-    double xv[12], kv[4], A[MAXLOC * MAXLOC];
+    double xv[12], kv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC];
     int64_t rc = 0;
     for (int64_t c = 0; c < ncells && rc == 0; ++c) {
         int any = 0;
         for (int i = 0; i < n; ++i) any |= slot[cell_node[c * n + i]] >= 0;
         if (!any) continue;
         gather_cell(dim, c, cell_vertex, coords, kappa, xv, kv);
-        oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A);
+        oracle_element_matrix(dim, degree, xv, kv, cstiff, cmass, A, Aa);
         for (int i = 0; i < n; ++i) {
             int64_t s = slot[cell_node[c * n + i]];
             if (s < 0) continue;
@@ -587,7 +601,7 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
                     cols[s * per + k] = col; cnt[s]++;
                 }
                 vals[s * per + k] += A[i * n + j];
-                abss[s * per + k] += fabs(A[i * n + j]);
+                abss[s * per + k] += Aa[i * n + j];
             }
         }
     }
@@ -630,23 +644,23 @@ int oracle_vec_rows(int kind, int dim, int degree, int64_t ncells, const int32_t
     if (!slot) return -1;
     for (int64_t r = 0; r < nrows; ++r) slot[r] = -1;
     for (int64_t s = 0; s < nsel; ++s) { slot[rows[s]] = s; out[s] = 0.0; out_abs[s] = 0.0; }
-    double xv[12], fv[4], A[MAXLOC * MAXLOC], be[MAXLOC];
+    double xv[12], fv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC], be[MAXLOC], ba[MAXLOC];
     for (int64_t c = 0; c < ncells; ++c) {
         int any = 0;
         for (int i = 0; i < n; ++i) any |= slot[cell_node[c * n + i]] >= 0;
         if (!any) continue;
         gather_cell(dim, c, cell_vertex, coords, field, xv, fv);
-        if (kind == 0) oracle_element_vector(dim, degree, xv, fv, be);
-        else oracle_element_matrix(dim, degree, xv, fv, cstiff, cmass, A);
+        if (kind == 0) oracle_element_vector(dim, degree, xv, fv, be, ba);
+        else oracle_element_matrix(dim, degree, xv, fv, cstiff, cmass, A, Aa);
         for (int i = 0; i < n; ++i) {
             int64_t s = slot[cell_node[c * n + i]];
             if (s < 0) continue;
-            if (kind == 0) { out[s] += be[i]; out_abs[s] += fabs(be[i]); }
+            if (kind == 0) { out[s] += be[i]; out_abs[s] += ba[i]; }
             else {
                 double t = 0.0, ta = 0.0;
                 for (int j = 0; j < n; ++j) {
-                    double u = A[i * n + j] * x[cell_node[c * n + j]];
-                    t += u; ta += fabs(u);
+                    double xj = x[cell_node[c * n + j]];
+                    t += A[i * n + j] * xj; ta += Aa[i * n + j] * fabs(xj);
                 }
                 out[s] += t; out_abs[s] += ta;
             }
