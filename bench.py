@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark of the cell-loop assembler on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path over the mesh):
+  P2 Lagrange Helmholtz form  kappa grad(u).grad(v) + u v  on the unit cube,
+  64^3 cubes x 6 Kuhn tetrahedra = 1,572,864 cells, interior vertices jittered
+  by U[-0.2h, 0.2h], kappa a P1 field U[0.5, 1.5], f a P1 field U[-1, 1],
+  x U[-1, 1]; FP64.  Step = CSR matrix assembly (WRITE) + source vector
+  assembly (WRITE) + matrix-free action y = A x (WRITE).
+Inputs are seeded and synthetic: the lattice mesh is shuffled (seeded) to
+emulate an unstructured numbering, then renumbered by the library's Hilbert
+renumbering, as the paper renumbers its meshes for locality.  Setup (sparsity,
+plans) is timed separately and is not part of a step.
+
+Prints ONE JSON line (rank 0).  value = cells / step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "assembled cells/s + % HBM roofline vs plain FP64; p50/p99 batched latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(n: int, degree: int, seed: int):
+    import fem_inputs as fi
+    st = fi.spawn_streams(seed)
+    m = fi.jitter_interior(fi.unit_cube(n), 0.2, st["mesh"])
+    cn, N = fi.node_map(m, degree)
+    kappa = fi.field(st["kappa"], m.nverts, 0.5, 1.5)
+    f = fi.field(st["f"], m.nverts, -1.0, 1.0)
+    x = fi.field(st["x"], N, -1.0, 1.0)
+    # seeded shuffle of cells, vertices and nodes (unstructured numbering)
+    rng = np.random.default_rng(seed + 1)
+    cp = rng.permutation(m.ncells)
+    cells, cn = fi.permute_cells(cp, m.cells, cn)
+    vp = rng.permutation(m.nverts)
+    vinv = np.empty_like(vp); vinv[vp] = np.arange(vp.size)
+    cells = vinv[cells].astype(np.int32)
+    coords, kappa, f = m.coords[vp], kappa[vp], f[vp]
+    npn = rng.permutation(N)
+    ninv = np.empty_like(npn); ninv[npn] = np.arange(N)
+    cn = ninv[cn].astype(np.int32)
+    x = x[npn]
+    return dict(cells=np.ascontiguousarray(cells), coords=np.ascontiguousarray(coords),
+                cn=np.ascontiguousarray(cn), N=N, kappa=kappa, f=f, x=x)
+
+
+def apply_perms(d, cp, vp, npn):
+    vinv = np.empty_like(vp); vinv[vp] = np.arange(vp.size, dtype=vp.dtype)
+    ninv = np.empty_like(npn); ninv[npn] = np.arange(npn.size, dtype=npn.dtype)
+    return dict(cells=np.ascontiguousarray(vinv[d["cells"][cp]]).astype(np.int32),
+                coords=np.ascontiguousarray(d["coords"][vp]),
+                cn=np.ascontiguousarray(ninv[d["cn"][cp]]).astype(np.int32), N=d["N"],
+                kappa=d["kappa"][vp].copy(), f=d["f"][vp].copy(), x=d["x"][npn].copy())
+
+
+def cpu_baseline(d, degree, sample_cells):
+    """The oracle, as it stands, on the first `sample_cells` cells of the same
+    (renumbered) mesh: sparsity + matrix + vector + action, one thread."""
+    import oracle
+    cells = d["cells"][:sample_cells]; cn = d["cn"][:sample_cells]
+    oracle.lib()
+    t0 = time.perf_counter()
+    rp, ci = oracle.sparsity(cn, d["N"])
+    oracle.assemble_mat(3, degree, cells, d["coords"], cn, d["kappa"], rp, ci)
+    oracle.assemble_vec(3, degree, cells, d["coords"], cn, d["f"], d["N"])
+    oracle.apply_action(3, degree, cells, d["coords"], cn, d["kappa"], d["x"], d["N"])
+    t = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": sample_cells / t, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_cells} cells of the same renumbered mesh, full step "
+                      f"(sparsity+mat+vec+action), {t:.1f} s single-threaded on {cpu}, "
+                      f"{len(os.sched_getaffinity(0))} host cores visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="cubes per side")
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=1501)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-renumber", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+                 "(one GPU's share of the mesh is the measured unit).")
+
+    import torch
+    from paper_1501_01809_amd import fem as F
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    d = build_inputs(args.n, args.degree, args.seed)
+    log(f"inputs: {d['cells'].shape[0]} cells, {d['N']} nodes ({time.perf_counter() - t0:.1f} s)")
+    ctx = F.Context(0)
+    C = d["cells"].shape[0]
+
+    def upload(dd):
+        return dict(cv=torch.from_numpy(dd["cells"]).to(dev), X=torch.from_numpy(dd["coords"]).to(dev),
+                    cn=torch.from_numpy(dd["cn"]).to(dev), kappa=torch.from_numpy(dd["kappa"]).to(dev),
+                    f=torch.from_numpy(dd["f"]).to(dev), x=torch.from_numpy(dd["x"]).to(dev))
+
+    form = F.form("helmholtz", 3, args.degree)
+    src = F.form("source", 3, args.degree)
+    setup = {}
+    g = upload(d)
+    if not args.no_renumber:
+        t = time.perf_counter()
+        a0 = F.Args(g["cv"], g["X"], g["cn"], d["N"], [g["kappa"]])
+        cp, vp, npn = F.fem_renumber(ctx, form, a0)
+        setup["renumber_ms"] = (time.perf_counter() - t) * 1e3
+        d = apply_perms(d, cp, vp, npn)
+        g = upload(d)
+    args_k = F.Args(g["cv"], g["X"], g["cn"], d["N"], [g["kappa"]])
+    args_f = F.Args(g["cv"], g["X"], g["cn"], d["N"], [g["f"]])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sp = F.fem_build_sparsity(ctx, g["cn"], d["N"])
+    torch.cuda.synchronize()
+    setup["sparsity_ms"] = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    mplan = F.fem_plan_create(ctx, form, args_k, sp)
+    setup["mat_plan_ms"] = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    vplan = F.fem_plan_create(ctx, form, args_k, None)
+    setup["vec_plan_ms"] = (time.perf_counter() - t) * 1e3
+    nnz = int(sp.col_idx.numel()); N = d["N"]
+    log(f"setup: nnz={nnz} {setup} mat plan {mplan.info()} vec plan {vplan.info()}")
+
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev)
+    b = torch.empty(N, dtype=torch.float64, device=dev)
+    y = torch.empty(N, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev: ev[0].record(stream)
+        F.fem_par_loop_assemble_mat(ctx, mplan, form, args_k, vals, sp, F.FEM_WRITE)
+        if ev: ev[1].record(stream)
+        F.fem_par_loop_assemble_vec(ctx, vplan, src, args_f, b, F.FEM_WRITE)
+        if ev: ev[2].record(stream)
+        F.fem_apply_action(ctx, vplan, form, args_k, g["x"], y, F.FEM_WRITE)
+        if ev: ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    per = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                     e[0].elapsed_time(e[3])] for e in evs])   # ms
+    ms_step = wall * 1e3 / args.steps
+    mat_ms, vec_ms, act_ms = (float(np.mean(per[:, i])) for i in range(3))
+
+    # algorithmic bytes per launch (one read of inputs and structure, one write of outputs)
+    V = d["coords"].shape[0]; nl = d["cn"].shape[1]
+    maps = 4 * C * nl + 4 * C * 4
+    vdata = 8 * V * 3 + 8 * V
+    mat_bytes = maps + vdata + 8 * (N + 1) + 4 * nnz + 8 * nnz
+    vec_bytes = maps + vdata + 8 * N
+    act_bytes = maps + vdata + 8 * N + 8 * N
+    gbs = lambda by, ms: by / (ms * 1e-3) / 1e9
+    ops = {
+        "mat": {"ms": mat_ms, "ms_min": float(per[:, 0].min()), "cells_per_s": C / (mat_ms * 1e-3),
+                "alg_bytes": mat_bytes, "GBps": gbs(mat_bytes, mat_ms),
+                "hbm_frac": gbs(mat_bytes, mat_ms) / HBM_PEAK_GBS,
+                "plan": mplan.info()},
+        "vec": {"ms": vec_ms, "cells_per_s": C / (vec_ms * 1e-3), "alg_bytes": vec_bytes,
+                "GBps": gbs(vec_bytes, vec_ms), "hbm_frac": gbs(vec_bytes, vec_ms) / HBM_PEAK_GBS},
+        "action": {"ms": act_ms, "cells_per_s": C / (act_ms * 1e-3), "alg_bytes": act_bytes,
+                   "GBps": gbs(act_bytes, act_ms), "hbm_frac": gbs(act_bytes, act_ms) / HBM_PEAK_GBS,
+                   "plan": vplan.info()},
+    }
+    out = {
+        "metric": METRIC,
+        "value": C / (ms_step * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"P{args.degree} Lagrange Helmholtz on the unit cube, {args.n}^3x6 "
+                               f"Kuhn tets ({C} cells, {N} DOFs, nnz {nnz}), jitter 0.2h, kappa P1 "
+                               f"U[0.5,1.5], f P1 U[-1,1]; step = CSR matrix + source vector + "
+                               f"matrix-free action, FP64",
+                   "cells": C, "dofs": N, "nnz": nnz, "renumbered": not args.no_renumber},
+        "roofline": {"bound": "hbm", "achieved": gbs(mat_bytes, mat_ms), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs(mat_bytes, mat_ms) / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_assemble_mat<3,2>", "alg_bytes_per_launch": mat_bytes},
+        "ops": ops,
+        "step_ms_p50": float(np.percentile(per[:, 3], 50)),
+        "step_ms_p99": float(np.percentile(per[:, 3], 99)),
+        "setup_ms": setup,
+        "host": platform.node(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C))
+        out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -57,7 +57,7 @@
  *
  * Determinism: results are bitwise reproducible run to run on the same
  * inputs and plan (the paper's colouring is deterministic, "Parloops and
- * kernels"); every sum is taken in ascending cell order.
+ * kernels"); every sum is taken in an order fixed by the plan.
  */
 #ifndef FEM_H
 #define FEM_H
@@ -190,7 +190,7 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
  * sparsity; with sp == NULL it serves fem_par_loop_assemble_vec and
  * fem_apply_action.  The plan partitions the rows of the output into
  * contiguous blocks, each owned by one workgroup that gathers every
- * contribution to its rows in ascending cell order (conflict-free INC without
+ * contribution to its rows in an order fixed by the plan (conflict-free INC without
  * atomics; "Access descriptors": only INC needs a schedule).  It references
  * the Maps' device arrays: rebuild it if their contents change.  Synchronises;
  * allocates device memory owned by the plan.

@@ -130,7 +130,8 @@ fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *n
 
 void free_plan_arrays(fem_plan *p)
 {
-    void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->inc_ptr, p->ent, p->gpos};
+    void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
+                    p->blk_q, p->q_ent, p->q_nrank, p->sched};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }
@@ -365,6 +366,10 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     std::vector<int64_t> hptr(nrows + 1);
     std::vector<int32_t> hent(ncells * nl);
     std::vector<int64_t> hrp;
+    std::vector<int32_t> hcv(ncells * (dim + 1));
+    if (!hcv.empty())
+        HIPC(hipMemcpyAsync(hcv.data(), args->cell_vertex->values, sizeof(int32_t) * hcv.size(),
+                            hipMemcpyDeviceToHost, s), "copy");
     HIPC(hipMemcpyAsync(hptr.data(), ptr.p, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost, s), "copy");
     if (!hent.empty())
         HIPC(hipMemcpyAsync(hent.data(), ent.p, sizeof(int32_t) * hent.size(), hipMemcpyDeviceToHost, s), "copy");
@@ -379,30 +384,115 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
 
     // Greedy partition of the rows into contiguous blocks bounded by the
     // rows a workgroup owns, the Mat values it can hold in LDS and the
-    // distinct cells its local index can address.  Keep at least ~2 blocks
-    // per CU when the problem is small.
+    // distinct cells it can address.  Keep at least ~2 blocks per CU when the
+    // problem is small.
     int64_t rows_cap = lim.rows_per_block;
     const int64_t want = 2 * (int64_t)ctx->num_cus;
     if (nrows < rows_cap * want) rows_cap = std::max<int64_t>(1, (nrows + want - 1) / want);
+    const int lbits = nl <= 4 ? 2 : nl <= 8 ? 3 : nl <= 16 ? 4 : 5;
     std::vector<int32_t> blk_row0{0}, blk_cptr{0}, bcell;
     std::vector<int32_t> stamp(ncells, -1), lpos(ncells, 0);
-    std::vector<uint16_t> hent16(hent.size());
+    // Dat plans: packed entries
+    std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
+    // Mat plans: schedule
+    std::vector<int32_t> blk_q{0}, q_ent{0}, q_nrank, rec_row, rec_cell;
+    std::vector<uint32_t> rec_hdr;
+    int max_ranks = 0;
+    bool rank_overflow = false;
     int64_t max_row = 0;
     if (is_mat)
         for (int64_t r = 0; r < nrows; ++r) max_row = std::max(max_row, hrp[r + 1] - hrp[r]);
-    const int lbits = nl <= 4 ? 2 : nl <= 8 ? 3 : nl <= 16 ? 4 : 5;
+    struct Item { int32_t rank, row, cell; uint32_t lcc, li; };
+    std::vector<std::vector<Item>> items;
     int32_t b = 0;
     int64_t rows = 0, slots = 0, cells = 0;
     size_t first_cell = 0;
     int64_t block_first_row = 0;
-    auto close_block = [&](int64_t next_row) {
-        std::sort(bcell.begin() + first_cell, bcell.end());
-        for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
-        for (int64_t r = block_first_row; r < next_row; ++r)
-            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
-                const int32_t e = hent[k];
-                hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
+    // Mat plans order every block's cells by the global key (colour, cell id)
+    // of a deterministic greedy colouring (no two cells of one colour share a
+    // node; the paper's PyOP2 colours its INC loops deterministically).  A row
+    // meets at most one cell per colour, so a chunk of consecutive cells of
+    // that order needs only a few rank steps; the key being global, every row
+    // sums its contributions in the same order, which keeps an assembled
+    // symmetric form bitwise symmetric.
+    std::vector<int32_t> colour;
+    if (is_mat) {
+        std::vector<int32_t> node_of(ncells * (int64_t)nl);
+        for (int64_t r = 0; r < nrows; ++r)
+            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) node_of[hent[k]] = (int32_t)r;
+        colour.assign(ncells, 0);
+        std::vector<int32_t> mark(64, -1);
+        for (int64_t c = 0; c < ncells; ++c) {
+            for (int l = 0; l < nl; ++l) {
+                const int32_t r = node_of[c * nl + l];
+                for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                    const int64_t c2 = hent[k] / nl;
+                    if (c2 >= c) break;                  // entries ascend by cell
+                    const int32_t col = colour[c2];
+                    if (col >= (int32_t)mark.size()) mark.resize(2 * col + 2, -1);
+                    mark[col] = (int32_t)c;
+                }
             }
+            int32_t col = 0;
+            while (col < (int32_t)mark.size() && mark[col] == (int32_t)c) ++col;
+            colour[c] = col;
+        }
+    }
+    auto close_block = [&](int64_t next_row) {
+        if (is_mat)
+            std::sort(bcell.begin() + first_cell, bcell.end(), [&](int32_t x, int32_t y) {
+                return colour[x] != colour[y] ? colour[x] < colour[y] : x < y;
+            });
+        else
+            std::sort(bcell.begin() + first_cell, bcell.end());
+        const int64_t nc = (int64_t)(bcell.size() - first_cell);
+        for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
+        if (!is_mat) {
+            for (int64_t r = block_first_row; r < next_row; ++r)
+                for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                    const int32_t e = hent[k];
+                    hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
+                }
+        } else {
+            const int CH = lim.chunk;
+            const int64_t nq = (nc + CH - 1) / CH;
+            items.assign(nq, {});
+            std::vector<int32_t> seen(nq);
+            std::vector<std::pair<int32_t, int32_t>> rowent;   // (position in block order, entry)
+            for (int64_t r = block_first_row; r < next_row; ++r) {
+                std::fill(seen.begin(), seen.end(), 0);
+                rowent.clear();
+                for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) rowent.push_back({lpos[hent[k] / nl], hent[k]});
+                std::sort(rowent.begin(), rowent.end());
+                for (const auto &pe : rowent) {
+                    const int32_t lc = pe.first, e = pe.second, c = e / nl;
+                    const int64_t q = lc / CH;
+                    const int32_t rank = seen[q]++;
+                    items[q].push_back({rank, (int32_t)r, c, (uint32_t)(lc % CH), (uint32_t)(e % nl)});
+                }
+            }
+            const int64_t rbase = hrp[block_first_row];
+            for (int64_t q = 0; q < nq; ++q) {
+                std::vector<Item> &v = items[q];
+                std::sort(v.begin(), v.end(), [](const Item &x, const Item &y) {
+                    return x.rank != y.rank ? x.rank < y.rank : x.row < y.row;
+                });
+                int32_t nr = 0;
+                for (const Item &it : v) {
+                    nr = std::max(nr, it.rank + 1);
+                    if (it.rank >= (1 << lim.rank_bits)) rank_overflow = true;
+                    const uint32_t base = (uint32_t)(hrp[it.row] - rbase);
+                    rec_hdr.push_back(base | (it.lcc << 15) | (it.li << (15 + lim.chunk_bits)) |
+                                      ((uint32_t)it.rank << (15 + lim.chunk_bits + lbits)));
+                    rec_row.push_back(it.row);
+                    rec_cell.push_back(it.cell);
+                }
+                max_ranks = std::max(max_ranks, (int)nr);
+                q_nrank.push_back(nr);
+                q_ent.push_back((int32_t)rec_hdr.size());
+            }
+            blk_q.push_back(blk_q.back() + (int32_t)nq);
+        }
         blk_row0.push_back((int32_t)next_row);
         blk_cptr.push_back((int32_t)bcell.size());
         first_cell = bcell.size();
@@ -434,6 +524,11 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         cells += fresh;
     }
     if (rows > 0) close_block(nrows);
+    if (rank_overflow)
+        return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row meets more than %d cells of one chunk",
+                    1 << lim.rank_bits);
+    if (is_mat && max_row > 65536)
+        return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row has more than 65536 columns");
 
     fem_plan *p = new (std::nothrow) fem_plan;
     if (!p) return fail(ctx, FEM_E_NOMEM, "plan_create: host allocation");
@@ -446,34 +541,43 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     p->cell_visits = (int64_t)bcell.size();
     p->cell_node = args->cell_node->values;
     p->row_ptr = is_mat ? sp->row_ptr : nullptr;
-    std::vector<int32_t> inc32(nrows + 1);
-    for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
+    p->max_ranks = max_ranks;
+    std::vector<int32_t> bverts(bcell.size() * (dim + 1));
+    for (size_t i = 0; i < bcell.size(); ++i)
+        for (int m = 0; m <= dim; ++m) bverts[i * (dim + 1) + m] = hcv[(int64_t)bcell[i] * (dim + 1) + m];
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(&p->blk_row0, blk_row0, &p->bytes, s);
     if (e == hipSuccess) e = upload(&p->blk_cptr, blk_cptr, &p->bytes, s);
     if (e == hipSuccess) e = upload(&p->bcell, bcell, &p->bytes, s);
-    if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
-    if (e == hipSuccess) e = upload(&p->ent, hent16, &p->bytes, s);
-    if (e == hipSuccess && is_mat) {
+    if (e == hipSuccess) e = upload(&p->bverts, bverts, &p->bytes, s);
+    if (!is_mat) {
+        std::vector<int32_t> inc32(nrows + 1);
+        for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
+        if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
+        if (e == hipSuccess) e = upload(&p->ent, hent16, &p->bytes, s);
+    } else {
+        p->nchunks = (int64_t)q_nrank.size();
         p->pos_bytes = max_row <= 256 ? 1 : 2;
-        if (max_row > 65536) {
-            free_plan_arrays(p);
-            delete p;
-            return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row has more than 65536 columns");
-        }
-        const int rowbytes = ((nl * p->pos_bytes + 3) / 4) * 4;
-        p->gstride = rowbytes / p->pos_bytes;
-        const size_t gbytes = (size_t)ncells * nl * rowbytes;
-        e = hipMalloc(&p->gpos, gbytes ? gbytes : 8);
-        if (e == hipSuccess) {
-            p->bytes += gbytes;
-            e = hipMemsetAsync(flag.p, 0, sizeof(int), s);
-        }
-        if (e == hipSuccess && gbytes)
-            e = hipMemsetAsync(p->gpos, 0, gbytes, s);
+        p->sched_words = 1 + (nl * p->pos_bytes + 3) / 4;
+        if (e == hipSuccess) e = upload(&p->blk_q, blk_q, &p->bytes, s);
+        if (e == hipSuccess) e = upload(&p->q_ent, q_ent, &p->bytes, s);
+        if (e == hipSuccess) e = upload(&p->q_nrank, q_nrank, &p->bytes, s);
+        const int64_t nrec = (int64_t)rec_hdr.size();
+        const size_t wbytes = sizeof(uint32_t) * (size_t)nrec * p->sched_words;
+        if (e == hipSuccess) e = hipMalloc((void **)&p->sched, wbytes ? wbytes : 8);
+        if (e == hipSuccess) p->bytes += wbytes;
+        DevBuf drow(s), dcell(s), dhdr(s);
+        if (e == hipSuccess) e = drow.alloc(sizeof(int32_t) * nrec);
+        if (e == hipSuccess) e = dcell.alloc(sizeof(int32_t) * nrec);
+        if (e == hipSuccess) e = dhdr.alloc(sizeof(uint32_t) * nrec);
+        if (e == hipSuccess && nrec) e = hipMemcpyAsync(drow.p, rec_row.data(), 4 * nrec, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && nrec) e = hipMemcpyAsync(dcell.p, rec_cell.data(), 4 * nrec, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && nrec) e = hipMemcpyAsync(dhdr.p, rec_hdr.data(), 4 * nrec, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(flag.p, 0, sizeof(int), s);
         if (e == hipSuccess)
-            e = femk::positions(ptr.as<int64_t>(), ent.as<int32_t>(), nl, args->cell_node->values, nl, nrows,
-                                sp->row_ptr, sp->col_idx, p->gpos, p->pos_bytes, p->gstride, flag.as<int>(), s);
+            e = femk::sched_positions(drow.as<int32_t>(), dcell.as<int32_t>(), dhdr.as<uint32_t>(), nrec,
+                                      args->cell_node->values, nl, sp->row_ptr, sp->col_idx, p->sched,
+                                      p->sched_words, p->pos_bytes, flag.as<int>(), s);
         int hflag = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -5,14 +5,15 @@
 // element tensor into the output (INC).  Here the INC is made conflict-free
 // and deterministic by owning OUTPUT ROWS instead of colouring cells: the plan
 // splits the rows into contiguous blocks; one workgroup owns a block and
-// visits, in ascending order, every cell incident to its rows.  Per chunk of
-// cells it
+// visits every cell incident to its rows, in an order fixed by the plan.  Per
+// chunk of cells it
 //   1. gathers the cells' vertex coordinates and P1 coefficients,
 //   2. computes the FP64 geometry (adjugate, |det J|, metric
 //      |det J| grad(l_m).grad(l_n)) and the element tensor from the exact
 //      reference integrals (generated straight-line FMA code), into LDS,
-//   3. lets every lane pull, for the rows it owns, the contributions of the
-//      chunk's cells in ascending cell order into an LDS accumulator,
+//   3. adds the chunk's contributions to the block's rows, held in LDS, in a
+//      static schedule whose steps touch distinct rows (Mat), or lets each
+//      lane sum the contributions to the rows it owns (Dat, action),
 // and finally writes its rows once, contiguously (the block's rows occupy one
 // contiguous range of the CSR values).  No atomics and no inter-workgroup
 // communication are used, so the result is bitwise reproducible; the price is
@@ -20,22 +21,25 @@
 #include "fem_internal.h"
 #include "fem_tables.h"
 
+#include <algorithm>
+
 namespace femk {
 namespace {
 
-constexpr int WG = 256;
 
 // Everything a kernel reads, by value: device pointers and scalars only.
 struct KArgs {
     const int32_t *__restrict__ blk_row0;
     const int32_t *__restrict__ blk_cptr;
     const int32_t *__restrict__ bcell;
+    const int32_t *__restrict__ bverts;
     const int32_t *__restrict__ inc_ptr;
     const uint16_t *__restrict__ ent;
-    const void *__restrict__ gpos;
-    int gstride;
+    const int32_t *__restrict__ blk_q;
+    const int32_t *__restrict__ q_ent;
+    const int32_t *__restrict__ q_nrank;
+    const uint32_t *__restrict__ sched;
     const int64_t *__restrict__ row_ptr;
-    const int32_t *__restrict__ cell_vertex;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
     const double *__restrict__ coeff;
@@ -49,13 +53,15 @@ KArgs kargs(const AsmArgs &a)
 {
     const fem_plan &p = *a.plan;
     KArgs k;
-    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell;
-    k.inc_ptr = p.inc_ptr; k.ent = p.ent; k.gpos = p.gpos; k.gstride = p.gstride;
-    k.row_ptr = a.row_ptr; k.cell_vertex = a.cell_vertex; k.coords = a.coords;
+    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts;
+    k.inc_ptr = p.inc_ptr; k.ent = p.ent;
+    k.blk_q = p.blk_q; k.q_ent = p.q_ent; k.q_nrank = p.q_nrank; k.sched = p.sched;
+    k.row_ptr = a.row_ptr; k.coords = a.coords;
     k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
     return k;
 }
+
 constexpr int LDS_DOUBLES = 163840 / 8;    // gfx950: 160 KiB of LDS per CU
 
 // ---------------------------------------------------------------- geometry
@@ -124,69 +130,32 @@ template <> struct Geo<3> {
     }
 };
 
-// Gather the cell's vertex coordinates and the P1 coefficient at its vertices.
-template <int D>
-__device__ __forceinline__ void gather_cell(int64_t c, const int32_t *__restrict__ cv,
-                                            const double *__restrict__ X,
-                                            const double *__restrict__ coef, double (&x)[D + 1][D],
-                                            double (&k)[D + 1])
-{
-#pragma unroll
-    for (int m = 0; m <= D; ++m) {
-        const int64_t v = cv[c * (D + 1) + m];
-#pragma unroll
-        for (int r = 0; r < D; ++r) x[m][r] = X[v * D + r];
-        k[m] = coef[v];
-    }
-}
-
-// P[k*NM + mn] = cstiff * kappa_k * G[mn]
-template <int D>
-__device__ __forceinline__ double cell_tensor_inputs(int64_t c, const KArgs &a,
-                                                     double (&P)[(D + 1) * Geo<D>::NM],
-                                                     double *madet)
-{
-    double x[D + 1][D], k[D + 1], G[Geo<D>::NM];
-    gather_cell<D>(c, a.cell_vertex, a.coords, a.coeff, x, k);
-    const double adet = Geo<D>::metric(x, G);
-#pragma unroll
-    for (int m = 0; m <= D; ++m) {
-        const double s = a.cstiff * k[m];
-#pragma unroll
-        for (int t = 0; t < Geo<D>::NM; ++t) P[m * Geo<D>::NM + t] = s * G[t];
-    }
-    *madet = a.cmass * adet;
-    return adet;
-}
-
-template <class T>
-__device__ __forceinline__ void mat_group(int g, const double *P, double madet, double *E)
-{
-    if constexpr (T::NG == 1) {
-        T::mat_group0(P, madet, E);
-    } else {
-        switch (g) {
-        case 0: T::mat_group0(P, madet, E); break;
-        case 1: T::mat_group1(P, madet, E); break;
-        case 2: T::mat_group2(P, madet, E); break;
-        default: T::mat_group3(P, madet, E); break;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- configs
 
-// CHUNK: cells evaluated per step; KR: rows owned per lane (rows per block =
-// KR*WG); SLOTS: Mat values accumulated in LDS per block.
+// Mat kernels: workgroups of MWG lanes, one row per lane; CHUNK cells are
+// evaluated per step (NG waves share a cell, one entry group each) and their
+// packed upper-triangle element tensors (E doubles each) live in LDS next to
+// the block's Mat values.
+constexpr int MWG = 512;
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CHUNK = 256, KR = 4, SLOTS = 10240 - 256 * 9; };
-template <> struct MatCfg<3, 1> { static constexpr int CHUNK = 256, KR = 2, SLOTS = 10240 - 256 * 16; };
-template <> struct MatCfg<2, 2> { static constexpr int CHUNK = 64, KR = 3, SLOTS = 10240 - 64 * 36; };
-template <> struct MatCfg<3, 2> { static constexpr int CHUNK = 64, KR = 2, SLOTS = LDS_DOUBLES - 64 * 100; };
-template <> struct MatCfg<2, 3> { static constexpr int CHUNK = 64, KR = 4, SLOTS = LDS_DOUBLES - 64 * 100; };
-template <> struct MatCfg<3, 3> { static constexpr int CHUNK = 16, KR = 2, SLOTS = LDS_DOUBLES - 16 * 400; };
+template <> struct MatCfg<2, 1> { static constexpr int CHUNK = 512, CB = 9, E = 6; };
+template <> struct MatCfg<3, 1> { static constexpr int CHUNK = 512, CB = 9, E = 10; };
+template <> struct MatCfg<2, 2> { static constexpr int CHUNK = 128, CB = 7, E = 21; };
+template <> struct MatCfg<3, 2> { static constexpr int CHUNK = 128, CB = 7, E = 55; };
+template <> struct MatCfg<2, 3> { static constexpr int CHUNK = 128, CB = 7, E = 55; };
+template <> struct MatCfg<3, 3> { static constexpr int CHUNK = 32, CB = 5, E = 210; };
+template <int D, int K> constexpr int mat_slots()
+{
+    return LDS_DOUBLES - MatCfg<D, K>::CHUNK * MatCfg<D, K>::E;
+}
 
-template <int D, int K> struct VecCfg { static constexpr int CHUNK = 256, KR = 8; };
+// Dat and action kernels: workgroups of VWG lanes, KR rows per lane; the
+// per-cell local vectors of the whole block live in LDS (VLDS doubles, two
+// workgroups per CU).
+constexpr int VWG = 512;
+constexpr int VKR = 2;
+constexpr int VLDS = LDS_DOUBLES / 2;
+constexpr int VPRE = 8;     // entries of a row fetched per batch
 
 template <int D, int K> struct TabOf;
 template <> struct TabOf<2, 1> { using T = femtab::Tab21; };
@@ -198,182 +167,250 @@ template <> struct TabOf<3, 3> { using T = femtab::Tab33; };
 
 constexpr int lbits_for(int nloc) { return nloc <= 4 ? 2 : nloc <= 8 ? 3 : nloc <= 16 ? 4 : 5; }
 
+template <class T>
+__device__ __forceinline__ void mat_group_n(int g, const double *P, double madet, double *E)
+{
+    if constexpr (T::NG == 1) {
+        T::mat_group0(P, madet, E);
+    } else if constexpr (T::NG == 4) {
+        switch (g) {
+        case 0: T::mat_group0(P, madet, E); break;
+        case 1: T::mat_group1(P, madet, E); break;
+        case 2: T::mat_group2(P, madet, E); break;
+        default: T::mat_group3(P, madet, E); break;
+        }
+    } else {
+        switch (g) {
+        case 0: T::mat_group0(P, madet, E); break;
+        case 1: T::mat_group1(P, madet, E); break;
+        case 2: T::mat_group2(P, madet, E); break;
+        case 3: T::mat_group3(P, madet, E); break;
+        case 4: T::mat_group4(P, madet, E); break;
+        case 5: T::mat_group5(P, madet, E); break;
+        case 6: T::mat_group6(P, madet, E); break;
+        default: T::mat_group7(P, madet, E); break;
+        }
+    }
+}
+
+// Vertex coordinates and P1 coefficient of one cell, gathered through the
+// plan's per-visit vertex ids.
+template <int D> struct CellIn {
+    double x[D + 1][D];
+    double k[D + 1];
+};
+
+template <int D>
+__device__ __forceinline__ void load_cell(const int32_t *__restrict__ bverts, int64_t visit,
+                                          const double *__restrict__ X, const double *__restrict__ coef,
+                                          CellIn<D> &c)
+{
+    int32_t v[D + 1];
+#pragma unroll
+    for (int m = 0; m <= D; ++m) v[m] = bverts[visit * (D + 1) + m];
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+#pragma unroll
+        for (int r = 0; r < D; ++r) c.x[m][r] = X[(int64_t)v[m] * D + r];
+        c.k[m] = coef[v[m]];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void tensor_inputs(const CellIn<D> &c, double cstiff, double cmass,
+                                              double (&P)[(D + 1) * Geo<D>::NM], double *madet)
+{
+    double G[Geo<D>::NM];
+    const double adet = Geo<D>::metric(c.x, G);
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+        const double s = cstiff * c.k[m];
+#pragma unroll
+        for (int t = 0; t < Geo<D>::NM; ++t) P[m * Geo<D>::NM + t] = s * G[t];
+    }
+    *madet = cmass * adet;
+}
+
 // ---------------------------------------------------------------- Mat
 
 template <int D, int K, typename PosT>
-__global__ __launch_bounds__(WG) void k_assemble_mat(KArgs a)
+__global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a)
 {
     using T = typename TabOf<D, K>::T;
-    using C = MatCfg<D, K>;
-    constexpr int NL = T::NLOC, NN = NL * NL, LB = lbits_for(NL);
+    using Cf = MatCfg<D, K>;
+    constexpr int NL = T::NLOC, NE = T::NE, LB = lbits_for(NL), CB = Cf::CB;
     constexpr int NP = (D + 1) * Geo<D>::NM;
-    __shared__ double E[C::CHUNK * NN];
-    __shared__ double acc[C::SLOTS];
+    constexpr int SLOTS = mat_slots<D, K>();
+    constexpr int PER = 4 / (int)sizeof(PosT);              // positions per word
+    constexpr int W = 1 + (NL + PER - 1) / PER;              // words per record
+    constexpr int MM = (Cf::CHUNK * NL + MWG - 1) / MWG;     // records per lane and chunk
+    static_assert(NE == Cf::E && (1 << CB) == Cf::CHUNK, "config");
+    static_assert(SLOTS < 32768, "slot offsets are 15-bit");
+    __shared__ double E[Cf::CHUNK * NE];
+    __shared__ double acc[SLOTS];
 
-    const KArgs &p = a;
     const int b = blockIdx.x, tid = threadIdx.x;
-    const int r0 = p.blk_row0[b], r1 = p.blk_row0[b + 1];
+    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
     const int64_t s0 = a.row_ptr[r0];
     const int nslots = (int)(a.row_ptr[r1] - s0);
-    for (int s = tid; s < nslots; s += WG) acc[s] = 0.0;
+    for (int s = tid; s < nslots; s += MWG) acc[s] = 0.0;
 
-    int cur[C::KR], end[C::KR], base[C::KR];
-#pragma unroll
-    for (int k = 0; k < C::KR; ++k) {
-        const int r = r0 + tid + WG * k;
-        if (r < r1) {
-            cur[k] = p.inc_ptr[r]; end[k] = p.inc_ptr[r + 1];
-            base[k] = (int)(a.row_ptr[r] - s0);
-        } else {
-            cur[k] = end[k] = base[k] = 0;
-        }
-    }
-    const int c0 = p.blk_cptr[b], nc = p.blk_cptr[b + 1] - c0;
+    const int q0 = a.blk_q[b], nq = a.blk_q[b + 1] - q0;
+    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
     const int wave = tid >> 6, lane = tid & 63;
     const int grp = wave % T::NG;
     const int slot = (wave / T::NG) * 64 + lane;
-    const PosT *__restrict__ gpos = (const PosT *)p.gpos;
-    const int gs = p.gstride;
-    __syncthreads();
+    const bool computes = slot < Cf::CHUNK;
 
-    for (int cs = 0; cs < nc; cs += C::CHUNK) {
-        if (slot < C::CHUNK && cs + slot < nc) {
-            const int64_t c = p.bcell[c0 + cs + slot];
-            double P[NP], madet;
-            cell_tensor_inputs<D>(c, a, P, &madet);
-            mat_group<T>(grp, P, madet, E + slot * NN);
-        }
-        __syncthreads();
-        const int cend = cs + C::CHUNK;
+    // records of the next chunk, fetched one chunk ahead
+    uint32_t rw[MM][W];
+    bool rv[MM];
+    auto fetch_records = [&](int q) {
+        const int e0 = a.q_ent[q], e1 = a.q_ent[q + 1];
 #pragma unroll
-        for (int k = 0; k < C::KR; ++k) {
-            while (cur[k] < end[k]) {
-                const unsigned pk = p.ent[cur[k]];
-                const int lc = (int)(pk >> LB);
-                if (lc >= cend) break;
-                const int li = (int)(pk & ((1u << LB) - 1));
-                const PosT *__restrict__ gp = gpos + (int64_t)cur[k] * gs;
-                const double *__restrict__ er = E + (lc - cs) * NN + li * NL;
-                double *__restrict__ ac = acc + base[k];
+        for (int m = 0; m < MM; ++m) {
+            const int e = e0 + tid + m * MWG;
+            rv[m] = e < e1;
+            if (rv[m]) {
 #pragma unroll
-                for (int j = 0; j < NL; ++j) ac[gp[j]] += er[j];
-                ++cur[k];
+                for (int w = 0; w < W; ++w) rw[m][w] = a.sched[(int64_t)e * W + w];
             }
         }
+    };
+    CellIn<D> cin;
+    if (computes && slot < nc) load_cell<D>(a.bverts, c0 + slot, a.coords, a.coeff, cin);
+    if (nq > 0) fetch_records(q0);
+    __syncthreads();
+
+    for (int qi = 0; qi < nq; ++qi) {
+        const int cs = qi * Cf::CHUNK;
+        if (computes && cs + slot < nc) {
+            double P[NP], madet;
+            tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
+            mat_group_n<T>(grp, P, madet, E + slot * NE);
+        }
+        uint32_t cw[MM][W];
+        bool cv[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            cv[m] = rv[m];
+#pragma unroll
+            for (int w = 0; w < W; ++w) cw[m][w] = rw[m][w];
+        }
+        const int nrank = a.q_nrank[q0 + qi];
+        if (qi + 1 < nq) {
+            fetch_records(q0 + qi + 1);
+            if (computes && cs + Cf::CHUNK + slot < nc)
+                load_cell<D>(a.bverts, c0 + cs + Cf::CHUNK + slot, a.coords, a.coeff, cin);
+        }
         __syncthreads();
+        for (int rk = 0; rk < nrank; ++rk) {
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                const uint32_t h = cw[m][0];
+                if (!cv[m] || (int)(h >> (15 + CB + LB)) != rk) continue;
+                const int base = (int)(h & 0x7fffu);
+                const int lcc = (int)((h >> 15) & ((1u << CB) - 1));
+                const int li = (int)((h >> (15 + CB)) & ((1u << LB) - 1));
+                const double *__restrict__ Ec = E + lcc * NE;
+                const int ul = li * (2 * NL - li - 1) / 2;
+                int pos[NL];
+#pragma unroll
+                for (int j = 0; j < NL; ++j)
+                    pos[j] = base + (int)((cw[m][1 + j / PER] >> (8 * sizeof(PosT) * (j % PER))) &
+                                          ((1u << (8 * sizeof(PosT))) - 1));
+                double t[NL];
+#pragma unroll
+                for (int j = 0; j < NL; ++j) t[j] = acc[pos[j]];
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    const int uj = j * (2 * NL - j - 1) / 2;
+                    t[j] += Ec[j >= li ? ul + j : uj + li];
+                }
+#pragma unroll
+                for (int j = 0; j < NL; ++j) acc[pos[j]] = t[j];
+            }
+            __syncthreads();
+        }
     }
     double *__restrict__ out = a.out + s0;
     if (a.inc) {
-        for (int s = tid; s < nslots; s += WG) out[s] += acc[s];
+        for (int s = tid; s < nslots; s += MWG) out[s] += acc[s];
     } else {
-        for (int s = tid; s < nslots; s += WG) out[s] = acc[s];
+        for (int s = tid; s < nslots; s += MWG) out[s] = acc[s];
     }
 }
 
-// ---------------------------------------------------------------- Dat (source)
+// ---------------------------------------------------------------- Dat / action
 
-template <int D, int K>
-__global__ __launch_bounds__(WG) void k_assemble_vec(KArgs a)
+template <int D, int K, bool ACTION>
+__global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
 {
     using T = typename TabOf<D, K>::T;
-    using C = VecCfg<D, K>;
-    constexpr int NL = T::NLOC, LB = lbits_for(NL);
-    __shared__ double bk[C::CHUNK * NL];
-    const KArgs &p = a;
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int r0 = p.blk_row0[b], r1 = p.blk_row0[b + 1];
-    int cur[C::KR], end[C::KR];
-    double acc[C::KR];
-#pragma unroll
-    for (int k = 0; k < C::KR; ++k) {
-        const int r = r0 + tid + WG * k;
-        cur[k] = r < r1 ? p.inc_ptr[r] : 0;
-        end[k] = r < r1 ? p.inc_ptr[r + 1] : 0;
-        acc[k] = 0.0;
-    }
-    const int c0 = p.blk_cptr[b], nc = p.blk_cptr[b + 1] - c0;
-    for (int cs = 0; cs < nc; cs += C::CHUNK) {
-        if (cs + tid < nc) {
-            const int64_t c = p.bcell[c0 + cs + tid];
-            double x[D + 1][D], f[D + 1];
-            gather_cell<D>(c, a.cell_vertex, a.coords, a.coeff, x, f);
-            T::vec(f, Geo<D>::absdet(x), bk + tid * NL);
-        }
-        __syncthreads();
-        const int cend = cs + C::CHUNK;
-#pragma unroll
-        for (int k = 0; k < C::KR; ++k) {
-            while (cur[k] < end[k]) {
-                const unsigned pk = p.ent[cur[k]];
-                const int lc = (int)(pk >> LB);
-                if (lc >= cend) break;
-                acc[k] += bk[(lc - cs) * NL + (int)(pk & ((1u << LB) - 1))];
-                ++cur[k];
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < C::KR; ++k) {
-        const int r = r0 + tid + WG * k;
-        if (r < r1) a.out[r] = a.inc ? a.out[r] + acc[k] : acc[k];
-    }
-}
-
-// ---------------------------------------------------------------- action
-
-template <int D, int K>
-__global__ __launch_bounds__(WG) void k_apply_action(KArgs a)
-{
-    using T = typename TabOf<D, K>::T;
-    using C = VecCfg<D, K>;
     constexpr int NL = T::NLOC, LB = lbits_for(NL);
     constexpr int NP = (D + 1) * Geo<D>::NM;
-    __shared__ double yk[C::CHUNK * NL];
-    const KArgs &p = a;
+    constexpr int CAP = VLDS / NL;
+    __shared__ double vk[CAP * NL];
     const int b = blockIdx.x, tid = threadIdx.x;
-    const int r0 = p.blk_row0[b], r1 = p.blk_row0[b + 1];
-    int cur[C::KR], end[C::KR];
-    double acc[C::KR];
+    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
+    int cur[VKR], end[VKR];
+    uint32_t pe[VKR][VPRE];
+    double acc[VKR];
 #pragma unroll
-    for (int k = 0; k < C::KR; ++k) {
-        const int r = r0 + tid + WG * k;
-        cur[k] = r < r1 ? p.inc_ptr[r] : 0;
-        end[k] = r < r1 ? p.inc_ptr[r + 1] : 0;
+    for (int k = 0; k < VKR; ++k) {
+        const int r = r0 + tid + VWG * k;
+        cur[k] = r < r1 ? a.inc_ptr[r] : 0;
+        end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
         acc[k] = 0.0;
+#pragma unroll
+        for (int m = 0; m < VPRE; ++m) pe[k][m] = cur[k] + m < end[k] ? a.ent[cur[k] + m] : 0u;
     }
-    const int c0 = p.blk_cptr[b], nc = p.blk_cptr[b + 1] - c0;
-    for (int cs = 0; cs < nc; cs += C::CHUNK) {
+    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
+    CellIn<D> cin;
+    double xl[ACTION ? NL : 1];
+    auto fetch = [&](int c) {
+        load_cell<D>(a.bverts, c0 + c, a.coords, a.coeff, cin);
+        if constexpr (ACTION) {
+            const int64_t cell = a.bcell[c0 + c];
+#pragma unroll
+            for (int j = 0; j < NL; ++j) xl[j] = a.x[a.cell_node[cell * NL + j]];
+        }
+    };
+    if (tid < nc) fetch(tid);
+    for (int cs = 0; cs < nc; cs += VWG) {
         if (cs + tid < nc) {
-            const int64_t c = p.bcell[c0 + cs + tid];
-            double P[NP], madet, xl[NL], yl[NL];
-            cell_tensor_inputs<D>(c, a, P, &madet);
+            double loc[NL];
+            if constexpr (ACTION) {
+                double P[NP], madet;
+                tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
 #pragma unroll
-            for (int j = 0; j < NL; ++j) {
-                xl[j] = a.x[a.cell_node[c * NL + j]];
-                yl[j] = 0.0;
+                for (int j = 0; j < NL; ++j) loc[j] = 0.0;
+                T::act(P, madet, xl, loc);
+            } else {
+                T::vec(cin.k, Geo<D>::absdet(cin.x), loc);
             }
-            T::act(P, madet, xl, yl);
 #pragma unroll
-            for (int j = 0; j < NL; ++j) yk[tid * NL + j] = yl[j];
+            for (int j = 0; j < NL; ++j) vk[(cs + tid) * NL + j] = loc[j];
         }
-        __syncthreads();
-        const int cend = cs + C::CHUNK;
+        if (cs + VWG + tid < nc) fetch(cs + VWG + tid);
+    }
+    __syncthreads();
+    // every row sums its cells' local values in ascending cell order
 #pragma unroll
-        for (int k = 0; k < C::KR; ++k) {
-            while (cur[k] < end[k]) {
-                const unsigned pk = p.ent[cur[k]];
-                const int lc = (int)(pk >> LB);
-                if (lc >= cend) break;
-                acc[k] += yk[(lc - cs) * NL + (int)(pk & ((1u << LB) - 1))];
-                ++cur[k];
-            }
+    for (int k = 0; k < VKR; ++k) {
+        while (cur[k] < end[k]) {
+#pragma unroll
+            for (int m = 0; m < VPRE; ++m)
+                if (cur[k] + m < end[k])
+                    acc[k] += vk[(int)(pe[k][m] >> LB) * NL + (int)(pe[k][m] & ((1u << LB) - 1))];
+            cur[k] += VPRE;
+#pragma unroll
+            for (int m = 0; m < VPRE; ++m) pe[k][m] = cur[k] + m < end[k] ? a.ent[cur[k] + m] : 0u;
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < C::KR; ++k) {
-        const int r = r0 + tid + WG * k;
+    for (int k = 0; k < VKR; ++k) {
+        const int r = r0 + tid + VWG * k;
         if (r < r1) a.out[r] = a.inc ? a.out[r] + acc[k] : acc[k];
     }
 }
@@ -382,9 +419,9 @@ template <int D, int K>
 hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
     if (a.plan->pos_bytes == 1)
-        hipLaunchKernelGGL((k_assemble_mat<D, K, uint8_t>), dim3(a.plan->nblk), dim3(WG), 0, s, kargs(a));
+        hipLaunchKernelGGL((k_assemble_mat<D, K, uint8_t>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
     else
-        hipLaunchKernelGGL((k_assemble_mat<D, K, uint16_t>), dim3(a.plan->nblk), dim3(WG), 0, s, kargs(a));
+        hipLaunchKernelGGL((k_assemble_mat<D, K, uint16_t>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
     return hipGetLastError();
 }
 
@@ -395,17 +432,22 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
     const int nloc = dim == 2 ? (degree + 1) * (degree + 2) / 2
                               : (degree + 1) * (degree + 2) * (degree + 3) / 6;
     const int lb = lbits_for(nloc);
-    out->cell_cap = 1 << (16 - lb);
     out->slot_cap = 0;
-#define FEM_LIM(D, K)                                                        \
-    if (dim == D && degree == K) {                                           \
-        if (is_mat) {                                                        \
-            out->rows_per_block = MatCfg<D, K>::KR * WG;                     \
-            out->slot_cap = MatCfg<D, K>::SLOTS;                             \
-        } else {                                                             \
-            out->rows_per_block = VecCfg<D, K>::KR * WG;                     \
-        }                                                                    \
-        return true;                                                         \
+    out->chunk = out->chunk_bits = out->rank_bits = 0;
+#define FEM_LIM(D, K)                                                             \
+    if (dim == D && degree == K) {                                                \
+        if (is_mat) {                                                             \
+            out->rows_per_block = MWG;                                            \
+            out->slot_cap = mat_slots<D, K>();                                    \
+            out->chunk = MatCfg<D, K>::CHUNK;                                     \
+            out->chunk_bits = MatCfg<D, K>::CB;                                   \
+            out->rank_bits = 32 - 15 - MatCfg<D, K>::CB - lb;                     \
+            out->cell_cap = 1 << 20;                                              \
+        } else {                                                                  \
+            out->rows_per_block = VKR * VWG;                                      \
+            out->cell_cap = std::min(1 << (16 - lb), VLDS / nloc);                \
+        }                                                                         \
+        return true;                                                              \
     }
     FEM_LIM(2, 1) FEM_LIM(2, 2) FEM_LIM(2, 3) FEM_LIM(3, 1) FEM_LIM(3, 2) FEM_LIM(3, 3)
 #undef FEM_LIM
@@ -427,13 +469,13 @@ namespace {
 template <int D, int K>
 hipError_t vec_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_assemble_vec<D, K>), dim3(a.plan->nblk), dim3(WG), 0, s, kargs(a));
+    hipLaunchKernelGGL((k_assemble_vec<D, K, false>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
     return hipGetLastError();
 }
 template <int D, int K>
 hipError_t action_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_apply_action<D, K>), dim3(a.plan->nblk), dim3(WG), 0, s, kargs(a));
+    hipLaunchKernelGGL((k_assemble_vec<D, K, true>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
     return hipGetLastError();
 }
 }  // namespace

@@ -15,24 +15,43 @@ struct fem_ctx {
 };
 
 // Plan of the row-owned deterministic INC (see fem_plan_create in fem.h).
+//
+// Rows are split into contiguous blocks; a workgroup owns one block and
+// visits the ascending list of cells incident to its rows (bcell, with their
+// vertex ids in bverts).
+//  * Dat/action plans: every row's incident entries (inc_ptr / ent, ascending
+//    cell) name a cell of the block list (local index) and the row's local
+//    index in that cell.
+//  * Mat plans: the block's cells are processed in chunks; the contributions of
+//    a chunk to the block's rows form a static schedule (sched, W words per
+//    record: header = row slot base | cell-in-chunk | local index | rank, then
+//    the positions of the cell's columns inside the row).  Records of equal
+//    rank touch distinct rows; every row adds its contributions in the order
+//    of the global key (colour, cell id) of a greedy cell colouring.
 struct fem_plan {
-    int is_mat = 0;              // 1: Mat plan (has gpos), 0: Dat/action plan
+    int is_mat = 0;
     int dim = 0, degree = 0, nloc = 0;
     int64_t ncells = 0, nrows = 0, nverts = 0;
     int64_t nnz = 0;
     int32_t nblk = 0;
-    int lbits = 0;               // bits of the local index in ent[]
-    int pos_bytes = 1;           // bytes per position in gpos (1 or 2)
-    int gstride = 0;             // gpos elements per entry (padded to 4 bytes)
+    int lbits = 0;               // bits of the local index
+    int pos_bytes = 1;           // bytes per position (1 or 2)
+    int sched_words = 0;         // 32-bit words per schedule record
+    int64_t nchunks = 0;
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
+    int max_ranks = 0;
     size_t bytes = 0;            // device bytes held
     // device arrays (owned)
     int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
     int32_t *blk_cptr = nullptr;  // [nblk+1] offsets into bcell
     int32_t *bcell = nullptr;     // ascending global cell ids of each block
-    int32_t *inc_ptr = nullptr;   // [nrows+1] entry range of each row
-    uint16_t *ent = nullptr;      // [ncells*nloc] (local cell << lbits) | local index
-    void *gpos = nullptr;         // [ncells*nloc*gstride] position of each column in the row
+    int32_t *bverts = nullptr;    // [visits][dim+1] vertex ids of each bcell entry
+    int32_t *inc_ptr = nullptr;   // Dat plans: [nrows+1] entry range of each row
+    uint16_t *ent = nullptr;      // Dat plans: (local cell << lbits) | local index
+    int32_t *blk_q = nullptr;     // Mat plans: [nblk+1] first chunk of each block
+    int32_t *q_ent = nullptr;     // Mat plans: [nchunks+1] record range of each chunk
+    int32_t *q_nrank = nullptr;   // Mat plans: [nchunks] ranks of each chunk
+    uint32_t *sched = nullptr;    // Mat plans: records
     // identity of what the plan was built for
     const int32_t *cell_node = nullptr;
     const int64_t *row_ptr = nullptr;
@@ -51,11 +70,12 @@ hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_
                        const int32_t *cmap, int nloc_c, int64_t nrows, int32_t *counts,
                        const int64_t *row_ptr, int32_t *col_idx, int *overflow, hipStream_t s);
 hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
-// gpos[e*gstride + j] = position of cmap(cell(e), j) inside row(e).
-hipError_t positions(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
-                     const int32_t *cmap, int nloc_c, int64_t nrows, const int64_t *row_ptr,
-                     const int32_t *col_idx, void *gpos, int pos_bytes, int gstride,
-                     int *missing, hipStream_t s);
+// Schedule records: words[i*W] = hdr[i]; words[i*W+1..] = positions of the
+// columns cmap(cell[i], j) inside row[i], pos_bytes each, packed little-endian.
+hipError_t sched_positions(const int32_t *rec_row, const int32_t *rec_cell, const uint32_t *hdr,
+                           int64_t nrec, const int32_t *cmap, int nloc_c, const int64_t *row_ptr,
+                           const int32_t *col_idx, uint32_t *words, int W, int pos_bytes,
+                           int *missing, hipStream_t s);
 hipError_t i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- assembly kernels (fem_assemble.hip) ----
@@ -78,8 +98,11 @@ hipError_t launch_action(const AsmArgs &a, hipStream_t s);
 // Per-(dim, degree) launch limits used by the plan builder.
 struct Limits {
     int rows_per_block;     // rows a workgroup can own
-    int slot_cap;           // Mat values a workgroup can accumulate (mat only)
-    int cell_cap;           // distinct cells per block (ent[] local-cell bits)
+    int slot_cap;           // Mat values a workgroup can accumulate (Mat only)
+    int cell_cap;           // distinct cells per block
+    int chunk;              // cells per chunk (Mat only)
+    int chunk_bits;         // log2(chunk)
+    int rank_bits;          // bits left for the rank in a Mat record header
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
 

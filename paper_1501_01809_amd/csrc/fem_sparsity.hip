@@ -191,29 +191,33 @@ __global__ __launch_bounds__(64) void k_row_columns(
     }
 }
 
-template <typename PosT>
-__global__ void k_positions(const int64_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_ent,
-                            int nloc_r, const int32_t *__restrict__ cmap, int nloc_c, int64_t nrows,
-                            const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-                            PosT *__restrict__ gpos, int gstride, int *__restrict__ missing)
+// One thread per schedule record: binary search of each column of the cell
+// inside the row, packed into 32-bit words after the record header.
+__global__ void k_sched_positions(const int32_t *__restrict__ rec_row, const int32_t *__restrict__ rec_cell,
+                                  const uint32_t *__restrict__ hdr, int64_t nrec,
+                                  const int32_t *__restrict__ cmap, int nloc_c,
+                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                                  uint32_t *__restrict__ words, int W, int pos_bytes, int *__restrict__ missing)
 {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nrows;
-         r += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrec;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = rec_row[i], c = rec_cell[i];
         const int64_t a = row_ptr[r], len = row_ptr[r + 1] - a;
-        for (int64_t k = inc_ptr[r]; k < inc_ptr[r + 1]; ++k) {
-            const int64_t c = inc_ent[k] / nloc_r;
-            for (int j = 0; j < nloc_c; ++j) {
-                const int32_t v = cmap[c * nloc_c + j];
-                int64_t lo = 0, hi = len - 1, at = -1;
-                while (lo <= hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    int32_t w = col_idx[a + mid];
-                    if (w == v) { at = mid; break; }
-                    if (w < v) lo = mid + 1; else hi = mid - 1;
-                }
-                if (at < 0) { atomicOr(missing, 1); at = 0; }
-                gpos[k * gstride + j] = (PosT)at;
+        uint32_t *w = words + i * W;
+        w[0] = hdr[i];
+        for (int k = 1; k < W; ++k) w[k] = 0;
+        const int per = 4 / pos_bytes;
+        for (int j = 0; j < nloc_c; ++j) {
+            const int32_t v = cmap[c * nloc_c + j];
+            int64_t lo = 0, hi = len - 1, at = -1;
+            while (lo <= hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int32_t x = col_idx[a + mid];
+                if (x == v) { at = mid; break; }
+                if (x < v) lo = mid + 1; else hi = mid - 1;
             }
+            if (at < 0) { atomicOr(missing, 1); at = 0; }
+            w[1 + j / per] |= (uint32_t)at << (8 * pos_bytes * (j % per));
         }
     }
 }
@@ -279,20 +283,14 @@ hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_
     return hipGetLastError();
 }
 
-hipError_t positions(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
-                     const int32_t *cmap, int nloc_c, int64_t nrows, const int64_t *row_ptr,
-                     const int32_t *col_idx, void *gpos, int pos_bytes, int gstride,
-                     int *missing, hipStream_t s)
+hipError_t sched_positions(const int32_t *rec_row, const int32_t *rec_cell, const uint32_t *hdr,
+                           int64_t nrec, const int32_t *cmap, int nloc_c, const int64_t *row_ptr,
+                           const int32_t *col_idx, uint32_t *words, int W, int pos_bytes,
+                           int *missing, hipStream_t s)
 {
-    if (nrows <= 0) return hipSuccess;
-    if (pos_bytes == 1)
-        hipLaunchKernelGGL(k_positions<uint8_t>, dim3(grid_for(nrows, 128)), dim3(128), 0, s, inc_ptr,
-                           inc_ent, nloc_r, cmap, nloc_c, nrows, row_ptr, col_idx, (uint8_t *)gpos,
-                           gstride, missing);
-    else
-        hipLaunchKernelGGL(k_positions<uint16_t>, dim3(grid_for(nrows, 128)), dim3(128), 0, s, inc_ptr,
-                           inc_ent, nloc_r, cmap, nloc_c, nrows, row_ptr, col_idx, (uint16_t *)gpos,
-                           gstride, missing);
+    if (nrec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sched_positions, dim3(grid_for(nrec, 256)), dim3(256), 0, s, rec_row, rec_cell, hdr,
+                       nrec, cmap, nloc_c, row_ptr, col_idx, words, W, pos_bytes, missing);
     return hipGetLastError();
 }
 

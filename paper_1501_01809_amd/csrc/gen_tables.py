@@ -166,6 +166,11 @@ def entry_expr(i, j, NM, stiff, mass):
     return lines
 
 
+def upper_index(i, j, n):
+    """Position of (i, j), i <= j, in the row-major packed upper triangle."""
+    return i * (2 * n - i + 1) // 2 + (j - i)
+
+
 def split_groups(entries, cost, G):
     """Greedy longest-processing-time partition of entries into G groups."""
     groups = [[] for _ in range(G)]
@@ -192,12 +197,13 @@ def emit(d, k, G):
     groups, load = split_groups(entries, cost, G)
     out.append(f"  // entry-group loads (terms): {load}")
     for g, grp in enumerate(groups):
+        out.append(f"  // entries of group {g}, written to the packed upper triangle E[NE]")
         out.append(f"  __device__ __forceinline__ static void mat_group{g}(const double* __restrict__ P, double madet, double* __restrict__ E) {{")
         for (i, j) in grp:
             out.append("    {")
             for l in entry_expr(i, j, NM, stiff, mass):
                 out.append("      " + l)
-            out.append(f"      E[{i * n + j}] = e;" + (f" E[{j * n + i}] = e;" if i != j else ""))
+            out.append(f"      E[{upper_index(i, j, n)}] = e;")
             out.append("    }")
         out.append("  }")
     out.append("  // upper triangle, row-major (i<=j), Eu[NE]")
@@ -242,7 +248,7 @@ def main(path):
     summary = []
     for d in (2, 3):
         for k in (1, 2, 3):
-            G = 1 if k == 1 else 4
+            G = 1 if k == 1 else (8 if (d, k) == (3, 3) else 4)
             code, nt = emit(d, k, G)
             parts.append(code)
             summary.append((d, k, nt))
