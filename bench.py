@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-renumber", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (3 launches) to calibrate the "
+                         "HBM byte counters of a profiler, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -115,6 +118,15 @@ def main():
     from paper_1501_01809_amd import fem as F
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": 8 * n, "calibrate_copy_bytes_written": 8 * n}))
+        return
     t0 = time.perf_counter()
     d = build_inputs(args.n, args.degree, args.seed)
     log(f"inputs: {d['cells'].shape[0]} cells, {d['N']} nodes ({time.perf_counter() - t0:.1f} s)")

@@ -131,7 +131,7 @@ fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *n
 void free_plan_arrays(fem_plan *p)
 {
     void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
-                    p->blk_q, p->q_ent, p->q_nrank, p->sched};
+                    p->blk_w, p->wq, p->pstream};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }
@@ -373,14 +373,26 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     HIPC(hipMemcpyAsync(hptr.data(), ptr.p, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost, s), "copy");
     if (!hent.empty())
         HIPC(hipMemcpyAsync(hent.data(), ent.p, sizeof(int32_t) * hent.size(), hipMemcpyDeviceToHost, s), "copy");
+    std::vector<int32_t> hci, hcn;
     if (is_mat) {
         hrp.resize(nrows + 1);
         HIPC(hipMemcpyAsync(hrp.data(), sp->row_ptr, sizeof(int64_t) * (nrows + 1), hipMemcpyDeviceToHost, s),
              "copy");
+        HIPC(hipStreamSynchronize(s), "sync");
+        if (hrp[nrows] != sp->nnz || hrp[0] != 0)
+            return fail(ctx, FEM_E_ARG, "plan_create: row_ptr does not span [0, nnz]");
+        hci.resize(sp->nnz);
+        hcn.resize(ncells * nl);
+        if (!hci.empty())
+            HIPC(hipMemcpyAsync(hci.data(), sp->col_idx, sizeof(int32_t) * hci.size(), hipMemcpyDeviceToHost, s),
+                 "copy");
+        if (!hcn.empty())
+            HIPC(hipMemcpyAsync(hcn.data(), args->cell_node->values, sizeof(int32_t) * hcn.size(),
+                                hipMemcpyDeviceToHost, s), "copy");
     }
     HIPC(hipStreamSynchronize(s), "sync");
-    if (is_mat && hrp[nrows] != sp->nnz)
-        return fail(ctx, FEM_E_ARG, "plan_create: row_ptr[nrows] differs from nnz");
+    for (int32_t c : hci)
+        if (c < 0 || c >= nrows) return fail(ctx, FEM_E_RANGE, "plan_create: a column index lies outside [0, ncols)");
 
     // Greedy partition of the rows into contiguous blocks bounded by the
     // rows a workgroup owns, the Mat values it can hold in LDS and the
@@ -394,57 +406,118 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     std::vector<int32_t> stamp(ncells, -1), lpos(ncells, 0);
     // Dat plans: packed entries
     std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
-    // Mat plans: schedule
-    std::vector<int32_t> blk_q{0}, q_ent{0}, q_nrank, rec_row, rec_cell;
-    std::vector<uint32_t> rec_hdr;
-    int max_ranks = 0;
-    bool rank_overflow = false;
-    int64_t max_row = 0;
-    if (is_mat)
-        for (int64_t r = 0; r < nrows; ++r) max_row = std::max(max_row, hrp[r + 1] - hrp[r]);
-    struct Item { int32_t rank, row, cell; uint32_t lcc, li; };
-    std::vector<std::vector<Item>> items;
+    // Mat plans: per-lane LDS index streams (see fem_plan)
+    const int MW = 512, NW = MW / 64;
+    const int SCAP = lim.slot_cap, CCH = lim.cell_cap, NE = lim.ne;
+    const int ZIDX = SCAP + CCH * NE;
+    std::vector<int32_t> blk_w{0}, wq;
+    std::vector<uint16_t> stream;
+    std::vector<int32_t> colmark(is_mat ? nrows : 0, -1);
+    std::vector<int32_t> slot_ptr, lane_ptr, lane_slots, cursor;
+    std::vector<uint16_t> con_idx, con_q;   // per contribution: LDS index of the entry, chunk
+    std::vector<int32_t> weight, order, bucket;
+    std::vector<std::vector<uint16_t>> lane_ent(MW);
+    int64_t nchunks = 0;
+    bool missing = false;
+    auto upper = [nl](int i, int j) { if (i > j) std::swap(i, j); return i * (2 * nl - i + 1) / 2 + (j - i); };
     int32_t b = 0;
     int64_t rows = 0, slots = 0, cells = 0;
     size_t first_cell = 0;
     int64_t block_first_row = 0;
-    // Mat plans order every block's cells by the global key (colour, cell id)
-    // of a deterministic greedy colouring (no two cells of one colour share a
-    // node; the paper's PyOP2 colours its INC loops deterministically).  A row
-    // meets at most one cell per colour, so a chunk of consecutive cells of
-    // that order needs only a few rank steps; the key being global, every row
-    // sums its contributions in the same order, which keeps an assembled
-    // symmetric form bitwise symmetric.
-    std::vector<int32_t> colour;
-    if (is_mat) {
-        std::vector<int32_t> node_of(ncells * (int64_t)nl);
-        for (int64_t r = 0; r < nrows; ++r)
-            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) node_of[hent[k]] = (int32_t)r;
-        colour.assign(ncells, 0);
-        std::vector<int32_t> mark(64, -1);
-        for (int64_t c = 0; c < ncells; ++c) {
-            for (int l = 0; l < nl; ++l) {
-                const int32_t r = node_of[c * nl + l];
-                for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
-                    const int64_t c2 = hent[k] / nl;
-                    if (c2 >= c) break;                  // entries ascend by cell
-                    const int32_t col = colour[c2];
-                    if (col >= (int32_t)mark.size()) mark.resize(2 * col + 2, -1);
-                    mark[col] = (int32_t)c;
+    // Builds the Mat streams of the block [block_first_row, next_row): every
+    // Mat value of the block collects its contributions (cell, li, lj) in
+    // ascending cell id, values are dealt to lanes by weight (sorted, snake
+    // order), and each lane's stream lists, per chunk, "open value" then the
+    // value's entries of that chunk.
+    auto mat_streams = [&](int64_t next_row, int64_t nc) {
+        const int64_t sbase = hrp[block_first_row];
+        const int ns = (int)(hrp[next_row] - sbase);
+        const int nq = (int)((nc + CCH - 1) / CCH);
+        slot_ptr.assign(ns + 1, 0);
+        // contributions, grouped by value, ascending cell within a value
+        for (int64_t r = block_first_row; r < next_row; ++r) {
+            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = (int32_t)(k - sbase);
+            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                const int32_t c = hent[k] / nl;
+                for (int lj = 0; lj < nl; ++lj) {
+                    const int32_t sl = colmark[hcn[(int64_t)c * nl + lj]];
+                    if (sl < 0) { missing = true; continue; }
+                    ++slot_ptr[sl + 1];
                 }
             }
-            int32_t col = 0;
-            while (col < (int32_t)mark.size() && mark[col] == (int32_t)c) ++col;
-            colour[c] = col;
+            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = -1;
         }
-    }
+        for (int t = 0; t < ns; ++t) slot_ptr[t + 1] += slot_ptr[t];
+        con_idx.resize(slot_ptr[ns]);
+        con_q.resize(slot_ptr[ns]);
+        cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
+        for (int64_t r = block_first_row; r < next_row; ++r) {
+            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = (int32_t)(k - sbase);
+            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                const int32_t e = hent[k], c = e / nl, li = e % nl, lc = lpos[c];
+                for (int lj = 0; lj < nl; ++lj) {
+                    const int32_t sl = colmark[hcn[(int64_t)c * nl + lj]];
+                    if (sl < 0) continue;
+                    const int32_t at = cursor[sl]++;
+                    con_idx[at] = (uint16_t)(SCAP + (lc % CCH) * NE + upper(li, lj));
+                    con_q[at] = (uint16_t)(lc / CCH);
+                }
+            }
+            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = -1;
+        }
+        // weights: per chunk touched, one open plus the entries
+        weight.assign(ns, 0);
+        int wmax = 0;
+        for (int t = 0; t < ns; ++t) {
+            int w = slot_ptr[t + 1] - slot_ptr[t];
+            for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1]; ++k)
+                w += (k == slot_ptr[t] || con_q[k] != con_q[k - 1]);
+            weight[t] = w;
+            wmax = std::max(wmax, w);
+        }
+        bucket.assign(wmax + 2, 0);
+        for (int t = 0; t < ns; ++t) ++bucket[wmax - weight[t] + 1];
+        for (int w = 0; w <= wmax; ++w) bucket[w + 1] += bucket[w];
+        order.resize(ns);
+        for (int t = 0; t < ns; ++t) order[bucket[wmax - weight[t]]++] = t;
+        lane_ptr.assign(MW + 1, 0);
+        auto lane_at = [MW](int p) { const int k = p % MW; return (p / MW) % 2 ? MW - 1 - k : k; };
+        for (int p = 0; p < ns; ++p) ++lane_ptr[lane_at(p) + 1];
+        for (int l = 0; l < MW; ++l) lane_ptr[l + 1] += lane_ptr[l];
+        lane_slots.resize(ns);
+        {
+            std::vector<int32_t> fill(lane_ptr.begin(), lane_ptr.end() - 1);
+            for (int p = 0; p < ns; ++p) lane_slots[fill[lane_at(p)]++] = order[p];
+        }
+        cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
+        for (int q = 0; q < nq; ++q) {
+            for (int l = 0; l < MW; ++l) {
+                std::vector<uint16_t> &le = lane_ent[l];
+                le.clear();
+                for (int32_t k = lane_ptr[l]; k < lane_ptr[l + 1]; ++k) {
+                    const int32_t t = lane_slots[k];
+                    int32_t &at = cursor[t];
+                    if (at == slot_ptr[t + 1] || con_q[at] != q) continue;
+                    le.push_back((uint16_t)t);
+                    while (at < slot_ptr[t + 1] && con_q[at] == q) le.push_back(con_idx[at++]);
+                }
+            }
+            for (int w = 0; w < NW; ++w) {
+                wq.push_back((int32_t)(stream.size() / 8));
+                size_t len = 0;
+                for (int l = 64 * w; l < 64 * w + 64; ++l) len = std::max(len, lane_ent[l].size());
+                const size_t nb = (len + 7) / 8;
+                for (size_t i = 0; i < nb; ++i)
+                    for (int l = 64 * w; l < 64 * w + 64; ++l)
+                        for (size_t j = 8 * i; j < 8 * i + 8; ++j)
+                            stream.push_back(j < lane_ent[l].size() ? lane_ent[l][j] : (uint16_t)ZIDX);
+            }
+        }
+        nchunks += nq;
+        blk_w.push_back((int32_t)wq.size());
+    };
     auto close_block = [&](int64_t next_row) {
-        if (is_mat)
-            std::sort(bcell.begin() + first_cell, bcell.end(), [&](int32_t x, int32_t y) {
-                return colour[x] != colour[y] ? colour[x] < colour[y] : x < y;
-            });
-        else
-            std::sort(bcell.begin() + first_cell, bcell.end());
+        std::sort(bcell.begin() + first_cell, bcell.end());
         const int64_t nc = (int64_t)(bcell.size() - first_cell);
         for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
         if (!is_mat) {
@@ -454,44 +527,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
                     hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
                 }
         } else {
-            const int CH = lim.chunk;
-            const int64_t nq = (nc + CH - 1) / CH;
-            items.assign(nq, {});
-            std::vector<int32_t> seen(nq);
-            std::vector<std::pair<int32_t, int32_t>> rowent;   // (position in block order, entry)
-            for (int64_t r = block_first_row; r < next_row; ++r) {
-                std::fill(seen.begin(), seen.end(), 0);
-                rowent.clear();
-                for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) rowent.push_back({lpos[hent[k] / nl], hent[k]});
-                std::sort(rowent.begin(), rowent.end());
-                for (const auto &pe : rowent) {
-                    const int32_t lc = pe.first, e = pe.second, c = e / nl;
-                    const int64_t q = lc / CH;
-                    const int32_t rank = seen[q]++;
-                    items[q].push_back({rank, (int32_t)r, c, (uint32_t)(lc % CH), (uint32_t)(e % nl)});
-                }
-            }
-            const int64_t rbase = hrp[block_first_row];
-            for (int64_t q = 0; q < nq; ++q) {
-                std::vector<Item> &v = items[q];
-                std::sort(v.begin(), v.end(), [](const Item &x, const Item &y) {
-                    return x.rank != y.rank ? x.rank < y.rank : x.row < y.row;
-                });
-                int32_t nr = 0;
-                for (const Item &it : v) {
-                    nr = std::max(nr, it.rank + 1);
-                    if (it.rank >= (1 << lim.rank_bits)) rank_overflow = true;
-                    const uint32_t base = (uint32_t)(hrp[it.row] - rbase);
-                    rec_hdr.push_back(base | (it.lcc << 15) | (it.li << (15 + lim.chunk_bits)) |
-                                      ((uint32_t)it.rank << (15 + lim.chunk_bits + lbits)));
-                    rec_row.push_back(it.row);
-                    rec_cell.push_back(it.cell);
-                }
-                max_ranks = std::max(max_ranks, (int)nr);
-                q_nrank.push_back(nr);
-                q_ent.push_back((int32_t)rec_hdr.size());
-            }
-            blk_q.push_back(blk_q.back() + (int32_t)nq);
+            mat_streams(next_row, nc);
         }
         blk_row0.push_back((int32_t)next_row);
         blk_cptr.push_back((int32_t)bcell.size());
@@ -509,7 +545,8 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
             close_block(r);
             fresh = hptr[r + 1] - hptr[r];
         }
-        if ((is_mat && rs > lim.slot_cap) || fresh > lim.cell_cap)
+        // (a Mat row whose cells exceed one chunk gets a block of several chunks)
+        if ((is_mat && rs > lim.slot_cap) || (!is_mat && fresh > lim.cell_cap))
             return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: row %lld is too long for one workgroup",
                         (long long)r);
         for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
@@ -524,11 +561,12 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         cells += fresh;
     }
     if (rows > 0) close_block(nrows);
-    if (rank_overflow)
-        return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row meets more than %d cells of one chunk",
-                    1 << lim.rank_bits);
-    if (is_mat && max_row > 65536)
-        return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: a row has more than 65536 columns");
+    if (missing) return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
+    if (is_mat) {
+        wq.push_back((int32_t)(stream.size() / 8));
+        if (stream.size() / 8 > (size_t)INT32_MAX)
+            return fail(ctx, FEM_E_OVERFLOW, "plan_create: Mat streams exceed 2^31 batches");
+    }
 
     fem_plan *p = new (std::nothrow) fem_plan;
     if (!p) return fail(ctx, FEM_E_NOMEM, "plan_create: host allocation");
@@ -541,7 +579,6 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     p->cell_visits = (int64_t)bcell.size();
     p->cell_node = args->cell_node->values;
     p->row_ptr = is_mat ? sp->row_ptr : nullptr;
-    p->max_ranks = max_ranks;
     std::vector<int32_t> bverts(bcell.size() * (dim + 1));
     for (size_t i = 0; i < bcell.size(); ++i)
         for (int m = 0; m <= dim; ++m) bverts[i * (dim + 1) + m] = hcv[(int64_t)bcell[i] * (dim + 1) + m];
@@ -556,36 +593,11 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
         if (e == hipSuccess) e = upload(&p->ent, hent16, &p->bytes, s);
     } else {
-        p->nchunks = (int64_t)q_nrank.size();
-        p->pos_bytes = max_row <= 256 ? 1 : 2;
-        p->sched_words = 1 + (nl * p->pos_bytes + 3) / 4;
-        if (e == hipSuccess) e = upload(&p->blk_q, blk_q, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->q_ent, q_ent, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->q_nrank, q_nrank, &p->bytes, s);
-        const int64_t nrec = (int64_t)rec_hdr.size();
-        const size_t wbytes = sizeof(uint32_t) * (size_t)nrec * p->sched_words;
-        if (e == hipSuccess) e = hipMalloc((void **)&p->sched, wbytes ? wbytes : 8);
-        if (e == hipSuccess) p->bytes += wbytes;
-        DevBuf drow(s), dcell(s), dhdr(s);
-        if (e == hipSuccess) e = drow.alloc(sizeof(int32_t) * nrec);
-        if (e == hipSuccess) e = dcell.alloc(sizeof(int32_t) * nrec);
-        if (e == hipSuccess) e = dhdr.alloc(sizeof(uint32_t) * nrec);
-        if (e == hipSuccess && nrec) e = hipMemcpyAsync(drow.p, rec_row.data(), 4 * nrec, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && nrec) e = hipMemcpyAsync(dcell.p, rec_cell.data(), 4 * nrec, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && nrec) e = hipMemcpyAsync(dhdr.p, rec_hdr.data(), 4 * nrec, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemsetAsync(flag.p, 0, sizeof(int), s);
-        if (e == hipSuccess)
-            e = femk::sched_positions(drow.as<int32_t>(), dcell.as<int32_t>(), dhdr.as<uint32_t>(), nrec,
-                                      args->cell_node->values, nl, sp->row_ptr, sp->col_idx, p->sched,
-                                      p->sched_words, p->pos_bytes, flag.as<int>(), s);
-        int hflag = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess && hflag) {
-            free_plan_arrays(p);
-            delete p;
-            return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
-        }
+        p->nchunks = nchunks;
+        p->stream_entries = (int64_t)stream.size();
+        if (e == hipSuccess) e = upload(&p->blk_w, blk_w, &p->bytes, s);
+        if (e == hipSuccess) e = upload(&p->wq, wq, &p->bytes, s);
+        if (e == hipSuccess) e = upload(&p->pstream, stream, &p->bytes, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -5,15 +5,14 @@
 // element tensor into the output (INC).  Here the INC is made conflict-free
 // and deterministic by owning OUTPUT ROWS instead of colouring cells: the plan
 // splits the rows into contiguous blocks; one workgroup owns a block and
-// visits every cell incident to its rows, in an order fixed by the plan.  Per
-// chunk of cells it
+// visits every cell incident to its rows, in an order fixed by the plan.  It
 //   1. gathers the cells' vertex coordinates and P1 coefficients,
 //   2. computes the FP64 geometry (adjugate, |det J|, metric
 //      |det J| grad(l_m).grad(l_n)) and the element tensor from the exact
 //      reference integrals (generated straight-line FMA code), into LDS,
-//   3. adds the chunk's contributions to the block's rows, held in LDS, in a
-//      static schedule whose steps touch distinct rows (Mat), or lets each
-//      lane sum the contributions to the rows it owns (Dat, action),
+//   3. sums, per output value, the entries that land on it, in ascending cell
+//      id: Mat values are held in LDS and walked by a per-lane index stream;
+//      Dat values are summed in registers by the lane owning the row,
 // and finally writes its rows once, contiguously (the block's rows occupy one
 // contiguous range of the CSR values).  No atomics and no inter-workgroup
 // communication are used, so the result is bitwise reproducible; the price is
@@ -35,10 +34,9 @@ struct KArgs {
     const int32_t *__restrict__ bverts;
     const int32_t *__restrict__ inc_ptr;
     const uint16_t *__restrict__ ent;
-    const int32_t *__restrict__ blk_q;
-    const int32_t *__restrict__ q_ent;
-    const int32_t *__restrict__ q_nrank;
-    const uint32_t *__restrict__ sched;
+    const int32_t *__restrict__ blk_w;
+    const int32_t *__restrict__ wq;
+    const uint4 *__restrict__ pstream;
     const int64_t *__restrict__ row_ptr;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
@@ -55,7 +53,7 @@ KArgs kargs(const AsmArgs &a)
     KArgs k;
     k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts;
     k.inc_ptr = p.inc_ptr; k.ent = p.ent;
-    k.blk_q = p.blk_q; k.q_ent = p.q_ent; k.q_nrank = p.q_nrank; k.sched = p.sched;
+    k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint4 *>(p.pstream);
     k.row_ptr = a.row_ptr; k.coords = a.coords;
     k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
@@ -63,6 +61,24 @@ KArgs kargs(const AsmArgs &a)
 }
 
 constexpr int LDS_DOUBLES = 163840 / 8;    // gfx950: 160 KiB of LDS per CU
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// and meets the other waves, but leaves global loads in flight (the waves of
+// these kernels communicate through LDS only; inputs are read-only and each
+// output element is written by one lane).  __syncthreads() would also drain
+// every outstanding global load, which defeats prefetching across stages.
+// The memory clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Wait for every global load this wave has issued (the data of a software
+// pipeline stage, issued one stage earlier).
+__device__ __forceinline__ void wait_loads()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
 
 // ---------------------------------------------------------------- geometry
 
@@ -132,22 +148,20 @@ template <> struct Geo<3> {
 
 // ---------------------------------------------------------------- configs
 
-// Mat kernels: workgroups of MWG lanes, one row per lane; CHUNK cells are
-// evaluated per step (NG waves share a cell, one entry group each) and their
-// packed upper-triangle element tensors (E doubles each) live in LDS next to
-// the block's Mat values.
+// Mat kernels: workgroups of MWG lanes (one per CU: they take all of its
+// LDS).  A chunk of CCH cells is computed LPC lanes per cell (each lane
+// evaluates NG/LPC entry groups of the element tensor); LDS holds, in
+// doubles, [0, SCAP) the block's Mat values, [SCAP, SCAP + CCH*NE) the
+// chunk's packed element tensors and one -0.0 at ZIDX.
 constexpr int MWG = 512;
+constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CHUNK = 512, CB = 9, E = 6; };
-template <> struct MatCfg<3, 1> { static constexpr int CHUNK = 512, CB = 9, E = 10; };
-template <> struct MatCfg<2, 2> { static constexpr int CHUNK = 128, CB = 7, E = 21; };
-template <> struct MatCfg<3, 2> { static constexpr int CHUNK = 128, CB = 7, E = 55; };
-template <> struct MatCfg<2, 3> { static constexpr int CHUNK = 128, CB = 7, E = 55; };
-template <> struct MatCfg<3, 3> { static constexpr int CHUNK = 32, CB = 5, E = 210; };
-template <int D, int K> constexpr int mat_slots()
-{
-    return LDS_DOUBLES - MatCfg<D, K>::CHUNK * MatCfg<D, K>::E;
-}
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 2048, LPC = 1; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 1536, LPC = 1; };
+template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1; };
+template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2; };
+template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4; };
+template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4; };
 
 // Dat and action kernels: workgroups of VWG lanes, KR rows per lane; the
 // per-cell local vectors of the whole block live in LDS (VLDS doubles, two
@@ -165,33 +179,18 @@ template <> struct TabOf<3, 1> { using T = femtab::Tab31; };
 template <> struct TabOf<3, 2> { using T = femtab::Tab32; };
 template <> struct TabOf<3, 3> { using T = femtab::Tab33; };
 
-constexpr int lbits_for(int nloc) { return nloc <= 4 ? 2 : nloc <= 8 ? 3 : nloc <= 16 ? 4 : 5; }
+template <int D, int K> struct MatLds {
+    static constexpr int NE = TabOf<D, K>::T::NE;
+    static constexpr int CCH = MatCfg<D, K>::CCH;
+    static constexpr int ECH = CCH * NE;                              // element tensors of a chunk
+    static constexpr int SCAP = (LDS_DOUBLES - ECH - 1) / 8 * 8;       // Mat values of a block
+    static constexpr int ZIDX = SCAP + ECH;                           // holds -0.0
+    static constexpr int TOTAL = ZIDX + 1;
+    static_assert(TOTAL <= LDS_DOUBLES && TOTAL <= 65536, "16-bit LDS indices");
+    static_assert(SCAP > 0, "room for Mat values");
+};
 
-template <class T>
-__device__ __forceinline__ void mat_group_n(int g, const double *P, double madet, double *E)
-{
-    if constexpr (T::NG == 1) {
-        T::mat_group0(P, madet, E);
-    } else if constexpr (T::NG == 4) {
-        switch (g) {
-        case 0: T::mat_group0(P, madet, E); break;
-        case 1: T::mat_group1(P, madet, E); break;
-        case 2: T::mat_group2(P, madet, E); break;
-        default: T::mat_group3(P, madet, E); break;
-        }
-    } else {
-        switch (g) {
-        case 0: T::mat_group0(P, madet, E); break;
-        case 1: T::mat_group1(P, madet, E); break;
-        case 2: T::mat_group2(P, madet, E); break;
-        case 3: T::mat_group3(P, madet, E); break;
-        case 4: T::mat_group4(P, madet, E); break;
-        case 5: T::mat_group5(P, madet, E); break;
-        case 6: T::mat_group6(P, madet, E); break;
-        default: T::mat_group7(P, madet, E); break;
-        }
-    }
-}
+constexpr int lbits_for(int nloc) { return nloc <= 4 ? 2 : nloc <= 8 ? 3 : nloc <= 16 ? 4 : 5; }
 
 // Vertex coordinates and P1 coefficient of one cell, gathered through the
 // plan's per-visit vertex ids.
@@ -233,111 +232,152 @@ __device__ __forceinline__ void tensor_inputs(const CellIn<D> &c, double cstiff,
 
 // ---------------------------------------------------------------- Mat
 
-template <int D, int K, typename PosT>
+template <int D>
+__device__ __forceinline__ void issue_verts(const int32_t *__restrict__ bverts, int visit, int32_t (&v)[D + 1])
+{
+    if constexpr (D == 3) {
+        const int4 q = *reinterpret_cast<const int4 *>(bverts + (int64_t)visit * 4);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int m = 0; m <= D; ++m) v[m] = bverts[(int64_t)visit * (D + 1) + m];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void issue_coords(const int32_t (&v)[D + 1], const double *__restrict__ X,
+                                             const double *__restrict__ coef, CellIn<D> &c)
+{
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+#pragma unroll
+        for (int r = 0; r < D; ++r) c.x[m][r] = X[(int64_t)v[m] * D + r];
+        c.k[m] = coef[v[m]];
+    }
+}
+
+// Entry groups [g0, g0 + NG/LPC) of a cell's packed element tensor.
+template <class T, int LPC>
+__device__ __forceinline__ void mat_part(int part, const double *P, double madet, double *E)
+{
+    if constexpr (T::NG == 1) {
+        T::mat_group0(P, madet, E);
+    } else if constexpr (LPC == 1) {
+        T::mat_group0(P, madet, E); T::mat_group1(P, madet, E);
+        T::mat_group2(P, madet, E); T::mat_group3(P, madet, E);
+    } else if constexpr (LPC == 2) {
+        if (part == 0) { T::mat_group0(P, madet, E); T::mat_group1(P, madet, E); }
+        else { T::mat_group2(P, madet, E); T::mat_group3(P, madet, E); }
+    } else {
+        static_assert(LPC == 4, "lanes per cell");
+        switch (part) {
+        case 0: T::mat_group0(P, madet, E); break;
+        case 1: T::mat_group1(P, madet, E); break;
+        case 2: T::mat_group2(P, madet, E); break;
+        default: T::mat_group3(P, madet, E); break;
+        }
+    }
+}
+
+// One batch of 8 stream indices of a lane.  Index i < SCAP opens Mat value i:
+// the running sum restarts from the value LDS holds there; any other index
+// adds the LDS double it names.  The running sum is stored back after every
+// index, so the open value always holds the lane's latest partial sum (no
+// separate flush).  All 8 loads are issued first: the value an opening index
+// reads is never written earlier in the same batch (a lane opens each value
+// once per chunk, and writes only the value it has open).
+template <int SCAP>
+__device__ __forceinline__ void pull_batch(const uint4 w, double *lds, uint32_t &cur, double &acc)
+{
+    const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
+    uint32_t idx[8];
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        idx[j] = (j & 1) ? (wd[j >> 1] >> 16) : (wd[j >> 1] & 0xffffu);
+        v[j] = lds[idx[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool open = idx[j] < (uint32_t)SCAP;
+        const double sum = acc + v[j];
+        acc = open ? v[j] : sum;
+        cur = open ? idx[j] : cur;
+        lds[cur] = acc;
+    }
+}
+
+// One workgroup per row block:
+//   set the block's Mat values to -0.0 (the identity of the sums);
+//   per chunk of cells: issue the lane's first stream batches, gather the
+//     cells, compute their element tensors into LDS, barrier, walk the
+//     stream, barrier;
+//   write the block's values out (one contiguous, coalesced range).
+template <int D, int K>
 __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a)
 {
     using T = typename TabOf<D, K>::T;
-    using Cf = MatCfg<D, K>;
-    constexpr int NL = T::NLOC, NE = T::NE, LB = lbits_for(NL), CB = Cf::CB;
+    using L = MatLds<D, K>;
+    constexpr int NE = T::NE, CCH = L::CCH, LPC = MatCfg<D, K>::LPC;
     constexpr int NP = (D + 1) * Geo<D>::NM;
-    constexpr int SLOTS = mat_slots<D, K>();
-    constexpr int PER = 4 / (int)sizeof(PosT);              // positions per word
-    constexpr int W = 1 + (NL + PER - 1) / PER;              // words per record
-    constexpr int MM = (Cf::CHUNK * NL + MWG - 1) / MWG;     // records per lane and chunk
-    static_assert(NE == Cf::E && (1 << CB) == Cf::CHUNK, "config");
-    static_assert(SLOTS < 32768, "slot offsets are 15-bit");
-    __shared__ double E[Cf::CHUNK * NE];
-    __shared__ double acc[SLOTS];
+    constexpr int ITEMS = CCH * LPC;
+    constexpr int PASSES = (ITEMS + MWG - 1) / MWG;
+    static_assert(T::NG % LPC == 0, "groups per lane");
+    __shared__ double lds[L::TOTAL];
 
     const int b = blockIdx.x, tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
     const int64_t s0 = a.row_ptr[r0];
-    const int nslots = (int)(a.row_ptr[r1] - s0);
-    for (int s = tid; s < nslots; s += MWG) acc[s] = 0.0;
-
-    const int q0 = a.blk_q[b], nq = a.blk_q[b + 1] - q0;
+    const int ns = (int)(a.row_ptr[r1] - s0);
     const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int grp = wave % T::NG;
-    const int slot = (wave / T::NG) * 64 + lane;
-    const bool computes = slot < Cf::CHUNK;
+    const int w0 = a.blk_w[b], nq = (a.blk_w[b + 1] - w0) >> 3;
+    for (int s = tid; s < ns; s += MWG) lds[s] = -0.0;
+    if (tid == 0) lds[L::ZIDX] = -0.0;
 
-    // records of the next chunk, fetched one chunk ahead
-    uint32_t rw[MM][W];
-    bool rv[MM];
-    auto fetch_records = [&](int q) {
-        const int e0 = a.q_ent[q], e1 = a.q_ent[q + 1];
+    uint32_t cur = L::ZIDX;    // writes before the first open go to ZIDX and store -0.0 there
+    double acc = -0.0;
+    for (int q = 0; q < nq; ++q) {
+        const int st = a.wq[w0 + 8 * q + wave];
+        const int nb = (a.wq[w0 + 8 * q + wave + 1] - st) >> 6;
+        const uint4 *__restrict__ ps = a.pstream + st + lane;
+        uint4 sv[NBMAX];
+        if (nb > 0) {
 #pragma unroll
-        for (int m = 0; m < MM; ++m) {
-            const int e = e0 + tid + m * MWG;
-            rv[m] = e < e1;
-            if (rv[m]) {
+            for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(i < nb ? i : nb - 1) * 64];
+        }
 #pragma unroll
-                for (int w = 0; w < W; ++w) rw[m][w] = a.sched[(int64_t)e * W + w];
+        for (int pass = 0; pass < PASSES; ++pass) {
+            const int item = tid + pass * MWG;
+            const int lcc = item % CCH, part = item / CCH;
+            const int lc = q * CCH + lcc;
+            if (item < ITEMS && lc < nc) {
+                int32_t v[D + 1];
+                CellIn<D> cin;
+                issue_verts<D>(a.bverts, c0 + lc, v);
+                issue_coords<D>(v, a.coords, a.coeff, cin);
+                double P[NP], madet;
+                tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
+                mat_part<T, LPC>(part, P, madet, lds + L::SCAP + lcc * NE);
             }
         }
-    };
-    CellIn<D> cin;
-    if (computes && slot < nc) load_cell<D>(a.bverts, c0 + slot, a.coords, a.coeff, cin);
-    if (nq > 0) fetch_records(q0);
-    __syncthreads();
-
-    for (int qi = 0; qi < nq; ++qi) {
-        const int cs = qi * Cf::CHUNK;
-        if (computes && cs + slot < nc) {
-            double P[NP], madet;
-            tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
-            mat_group_n<T>(grp, P, madet, E + slot * NE);
-        }
-        uint32_t cw[MM][W];
-        bool cv[MM];
+        lds_barrier();
+        for (int g = 0; g < nb; g += NBMAX) {
+            if (g > 0) {
 #pragma unroll
-        for (int m = 0; m < MM; ++m) {
-            cv[m] = rv[m];
-#pragma unroll
-            for (int w = 0; w < W; ++w) cw[m][w] = rw[m][w];
-        }
-        const int nrank = a.q_nrank[q0 + qi];
-        if (qi + 1 < nq) {
-            fetch_records(q0 + qi + 1);
-            if (computes && cs + Cf::CHUNK + slot < nc)
-                load_cell<D>(a.bverts, c0 + cs + Cf::CHUNK + slot, a.coords, a.coeff, cin);
-        }
-        __syncthreads();
-        for (int rk = 0; rk < nrank; ++rk) {
-#pragma unroll
-            for (int m = 0; m < MM; ++m) {
-                const uint32_t h = cw[m][0];
-                if (!cv[m] || (int)(h >> (15 + CB + LB)) != rk) continue;
-                const int base = (int)(h & 0x7fffu);
-                const int lcc = (int)((h >> 15) & ((1u << CB) - 1));
-                const int li = (int)((h >> (15 + CB)) & ((1u << LB) - 1));
-                const double *__restrict__ Ec = E + lcc * NE;
-                const int ul = li * (2 * NL - li - 1) / 2;
-                int pos[NL];
-#pragma unroll
-                for (int j = 0; j < NL; ++j)
-                    pos[j] = base + (int)((cw[m][1 + j / PER] >> (8 * sizeof(PosT) * (j % PER))) &
-                                          ((1u << (8 * sizeof(PosT))) - 1));
-                double t[NL];
-#pragma unroll
-                for (int j = 0; j < NL; ++j) t[j] = acc[pos[j]];
-#pragma unroll
-                for (int j = 0; j < NL; ++j) {
-                    const int uj = j * (2 * NL - j - 1) / 2;
-                    t[j] += Ec[j >= li ? ul + j : uj + li];
-                }
-#pragma unroll
-                for (int j = 0; j < NL; ++j) acc[pos[j]] = t[j];
+                for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(g + i < nb ? g + i : nb - 1) * 64];
             }
-            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NBMAX; ++i)
+                if (g + i < nb) pull_batch<L::SCAP>(sv[i], lds, cur, acc);
         }
+        lds_barrier();
     }
     double *__restrict__ out = a.out + s0;
     if (a.inc) {
-        for (int s = tid; s < nslots; s += MWG) out[s] += acc[s];
+        for (int s = tid; s < ns; s += MWG) out[s] += lds[s];
     } else {
-        for (int s = tid; s < nslots; s += MWG) out[s] = acc[s];
+        for (int s = tid; s < ns; s += MWG) out[s] = lds[s];
     }
 }
 
@@ -394,7 +434,7 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
         }
         if (cs + VWG + tid < nc) fetch(cs + VWG + tid);
     }
-    __syncthreads();
+    lds_barrier();
     // every row sums its cells' local values in ascending cell order
 #pragma unroll
     for (int k = 0; k < VKR; ++k) {
@@ -418,10 +458,7 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
 template <int D, int K>
 hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    if (a.plan->pos_bytes == 1)
-        hipLaunchKernelGGL((k_assemble_mat<D, K, uint8_t>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
-    else
-        hipLaunchKernelGGL((k_assemble_mat<D, K, uint16_t>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
+    hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
     return hipGetLastError();
 }
 
@@ -433,16 +470,13 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
                               : (degree + 1) * (degree + 2) * (degree + 3) / 6;
     const int lb = lbits_for(nloc);
     out->slot_cap = 0;
-    out->chunk = out->chunk_bits = out->rank_bits = 0;
+    out->ne = nloc * (nloc + 1) / 2;
 #define FEM_LIM(D, K)                                                             \
     if (dim == D && degree == K) {                                                \
         if (is_mat) {                                                             \
-            out->rows_per_block = MWG;                                            \
-            out->slot_cap = mat_slots<D, K>();                                    \
-            out->chunk = MatCfg<D, K>::CHUNK;                                     \
-            out->chunk_bits = MatCfg<D, K>::CB;                                   \
-            out->rank_bits = 32 - 15 - MatCfg<D, K>::CB - lb;                     \
-            out->cell_cap = 1 << 20;                                              \
+            out->rows_per_block = MatLds<D, K>::SCAP;                             \
+            out->slot_cap = MatLds<D, K>::SCAP;                                   \
+            out->cell_cap = MatLds<D, K>::CCH;                                    \
         } else {                                                                  \
             out->rows_per_block = VKR * VWG;                                      \
             out->cell_cap = std::min(1 << (16 - lb), VLDS / nloc);                \

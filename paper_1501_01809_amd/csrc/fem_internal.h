@@ -22,12 +22,19 @@ struct fem_ctx {
 //  * Dat/action plans: every row's incident entries (inc_ptr / ent, ascending
 //    cell) name a cell of the block list (local index) and the row's local
 //    index in that cell.
-//  * Mat plans: the block's cells are processed in chunks; the contributions of
-//    a chunk to the block's rows form a static schedule (sched, W words per
-//    record: header = row slot base | cell-in-chunk | local index | rank, then
-//    the positions of the cell's columns inside the row).  Records of equal
-//    rank touch distinct rows; every row adds its contributions in the order
-//    of the global key (colour, cell id) of a greedy cell colouring.
+//  * Mat plans: the block's cells are processed in chunks of at most Limits::cell_cap
+//    cells whose packed element tensors sit in LDS together with the block's
+//    Mat values.  Every lane of the workgroup owns a set of the block's Mat
+//    values and walks its own stream of 16-bit LDS indices: an index below
+//    the value area's size opens that value (the running sum restarts from
+//    the value held there), any other index adds one element-tensor entry
+//    (or -0.0, the identity, for padding).  A value's entries come in
+//    ascending cell id, the same order in every block, so the sums are
+//    reproducible and an assembled symmetric form is bitwise symmetric.
+//    The stream of (chunk q, wave w) of a block starts at uint4 index
+//    wq[blk_w[b] + 8q + w] and ends where the next one starts; inside it,
+//    batch i of lane l is the uint4 at start + 64 i + l (8 indices, the
+//    first in the low half of .x).
 struct fem_plan {
     int is_mat = 0;
     int dim = 0, degree = 0, nloc = 0;
@@ -35,11 +42,9 @@ struct fem_plan {
     int64_t nnz = 0;
     int32_t nblk = 0;
     int lbits = 0;               // bits of the local index
-    int pos_bytes = 1;           // bytes per position (1 or 2)
-    int sched_words = 0;         // 32-bit words per schedule record
-    int64_t nchunks = 0;
+    int64_t nchunks = 0;         // Mat plans: chunks over all blocks
+    int64_t stream_entries = 0;  // Mat plans: 16-bit stream entries (padding included)
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
-    int max_ranks = 0;
     size_t bytes = 0;            // device bytes held
     // device arrays (owned)
     int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
@@ -48,10 +53,9 @@ struct fem_plan {
     int32_t *bverts = nullptr;    // [visits][dim+1] vertex ids of each bcell entry
     int32_t *inc_ptr = nullptr;   // Dat plans: [nrows+1] entry range of each row
     uint16_t *ent = nullptr;      // Dat plans: (local cell << lbits) | local index
-    int32_t *blk_q = nullptr;     // Mat plans: [nblk+1] first chunk of each block
-    int32_t *q_ent = nullptr;     // Mat plans: [nchunks+1] record range of each chunk
-    int32_t *q_nrank = nullptr;   // Mat plans: [nchunks] ranks of each chunk
-    uint32_t *sched = nullptr;    // Mat plans: records
+    int32_t *blk_w = nullptr;     // Mat plans: [nblk+1] first (chunk, wave) stream of each block
+    int32_t *wq = nullptr;        // Mat plans: [streams+1] first uint4 of each (chunk, wave) stream
+    uint16_t *pstream = nullptr;  // Mat plans: the streams
     // identity of what the plan was built for
     const int32_t *cell_node = nullptr;
     const int64_t *row_ptr = nullptr;
@@ -70,12 +74,6 @@ hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_
                        const int32_t *cmap, int nloc_c, int64_t nrows, int32_t *counts,
                        const int64_t *row_ptr, int32_t *col_idx, int *overflow, hipStream_t s);
 hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
-// Schedule records: words[i*W] = hdr[i]; words[i*W+1..] = positions of the
-// columns cmap(cell[i], j) inside row[i], pos_bytes each, packed little-endian.
-hipError_t sched_positions(const int32_t *rec_row, const int32_t *rec_cell, const uint32_t *hdr,
-                           int64_t nrec, const int32_t *cmap, int nloc_c, const int64_t *row_ptr,
-                           const int32_t *col_idx, uint32_t *words, int W, int pos_bytes,
-                           int *missing, hipStream_t s);
 hipError_t i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- assembly kernels (fem_assemble.hip) ----
@@ -98,11 +96,9 @@ hipError_t launch_action(const AsmArgs &a, hipStream_t s);
 // Per-(dim, degree) launch limits used by the plan builder.
 struct Limits {
     int rows_per_block;     // rows a workgroup can own
-    int slot_cap;           // Mat values a workgroup can accumulate (Mat only)
-    int cell_cap;           // distinct cells per block
-    int chunk;              // cells per chunk (Mat only)
-    int chunk_bits;         // log2(chunk)
-    int rank_bits;          // bits left for the rank in a Mat record header
+    int slot_cap;           // Mat values a workgroup holds in LDS (Mat only)
+    int cell_cap;           // distinct cells per block (Mat: per chunk)
+    int ne;                 // doubles per packed element tensor (Mat only)
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
 

@@ -191,37 +191,6 @@ __global__ __launch_bounds__(64) void k_row_columns(
     }
 }
 
-// One thread per schedule record: binary search of each column of the cell
-// inside the row, packed into 32-bit words after the record header.
-__global__ void k_sched_positions(const int32_t *__restrict__ rec_row, const int32_t *__restrict__ rec_cell,
-                                  const uint32_t *__restrict__ hdr, int64_t nrec,
-                                  const int32_t *__restrict__ cmap, int nloc_c,
-                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-                                  uint32_t *__restrict__ words, int W, int pos_bytes, int *__restrict__ missing)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrec;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = rec_row[i], c = rec_cell[i];
-        const int64_t a = row_ptr[r], len = row_ptr[r + 1] - a;
-        uint32_t *w = words + i * W;
-        w[0] = hdr[i];
-        for (int k = 1; k < W; ++k) w[k] = 0;
-        const int per = 4 / pos_bytes;
-        for (int j = 0; j < nloc_c; ++j) {
-            const int32_t v = cmap[c * nloc_c + j];
-            int64_t lo = 0, hi = len - 1, at = -1;
-            while (lo <= hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                const int32_t x = col_idx[a + mid];
-                if (x == v) { at = mid; break; }
-                if (x < v) lo = mid + 1; else hi = mid - 1;
-            }
-            if (at < 0) { atomicOr(missing, 1); at = 0; }
-            w[1 + j / per] |= (uint32_t)at << (8 * pos_bytes * (j % per));
-        }
-    }
-}
-
 inline int grid_for(int64_t n, int threads)
 {
     int64_t g = (n + threads - 1) / threads;
@@ -280,17 +249,6 @@ hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_
     int64_t g = nrows < 32768 ? nrows : 32768;
     hipLaunchKernelGGL(k_row_columns, dim3((unsigned)g), dim3(64), 0, s, inc_ptr, inc_ent, nloc_r,
                        cmap, nloc_c, nrows, counts, row_ptr, col_idx, overflow);
-    return hipGetLastError();
-}
-
-hipError_t sched_positions(const int32_t *rec_row, const int32_t *rec_cell, const uint32_t *hdr,
-                           int64_t nrec, const int32_t *cmap, int nloc_c, const int64_t *row_ptr,
-                           const int32_t *col_idx, uint32_t *words, int W, int pos_bytes,
-                           int *missing, hipStream_t s)
-{
-    if (nrec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sched_positions, dim3(grid_for(nrec, 256)), dim3(256), 0, s, rec_row, rec_cell, hdr,
-                       nrec, cmap, nloc_c, row_ptr, col_idx, words, W, pos_bytes, missing);
     return hipGetLastError();
 }
 

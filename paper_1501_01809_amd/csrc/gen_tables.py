@@ -248,7 +248,7 @@ def main(path):
     summary = []
     for d in (2, 3):
         for k in (1, 2, 3):
-            G = 1 if k == 1 else (8 if (d, k) == (3, 3) else 4)
+            G = 1 if k == 1 else 4
             code, nt = emit(d, k, G)
             parts.append(code)
             summary.append((d, k, nt))
