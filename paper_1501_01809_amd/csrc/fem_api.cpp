@@ -131,7 +131,7 @@ fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *n
 void free_plan_arrays(fem_plan *p)
 {
     void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
-                    p->blk_w, p->wq, p->pstream};
+                    p->blk_hdr, p->blk_w, p->wq, p->pstream};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }
@@ -415,7 +415,8 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     std::vector<int32_t> colmark(is_mat ? nrows : 0, -1);
     std::vector<int32_t> slot_ptr, lane_ptr, lane_slots, cursor;
     std::vector<uint16_t> con_idx, con_q;   // per contribution: LDS index of the entry, chunk
-    std::vector<int32_t> weight, order, bucket;
+    std::vector<int32_t> weight, order, bucket, lane_of, load;
+    std::vector<std::vector<int32_t>> by_load;
     std::vector<std::vector<uint16_t>> lane_ent(MW);
     int64_t nchunks = 0;
     bool missing = false;
@@ -426,9 +427,9 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     int64_t block_first_row = 0;
     // Builds the Mat streams of the block [block_first_row, next_row): every
     // Mat value of the block collects its contributions (cell, li, lj) in
-    // ascending cell id, values are dealt to lanes by weight (sorted, snake
-    // order), and each lane's stream lists, per chunk, "open value" then the
-    // value's entries of that chunk.
+    // ascending cell id, values are dealt to lanes by weight (one open per
+    // chunk touched plus the entries), and each lane's stream lists, per
+    // chunk, "open value" then the value's entries of that chunk.
     auto mat_streams = [&](int64_t next_row, int64_t nc) {
         const int64_t sbase = hrp[block_first_row];
         const int ns = (int)(hrp[next_row] - sbase);
@@ -480,14 +481,32 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         for (int w = 0; w <= wmax; ++w) bucket[w + 1] += bucket[w];
         order.resize(ns);
         for (int t = 0; t < ns; ++t) order[bucket[wmax - weight[t]]++] = t;
+        // longest-processing-time: each value, heaviest first, goes to the
+        // least-loaded lane (loads only grow, so a bucket queue keyed by load
+        // finds it); lanes enter in wave-interleaved order so ties spread
+        // over the waves
+        lane_of.resize(ns);
+        load.assign(MW, 0);
+        for (auto &v : by_load) v.clear();
+        if (by_load.empty()) by_load.resize(1);
+        for (int l = MW - 1; l >= 0; --l) by_load[0].push_back((l % NW) * 64 + l / NW);
+        for (int p = 0, m = 0; p < ns; ++p) {
+            while (by_load[m].empty()) ++m;
+            const int l = by_load[m].back();
+            by_load[m].pop_back();
+            const int t = order[p];
+            lane_of[t] = l;
+            load[l] += weight[t];
+            if ((int)by_load.size() <= load[l]) by_load.resize(load[l] + 1);
+            by_load[load[l]].push_back(l);
+        }
         lane_ptr.assign(MW + 1, 0);
-        auto lane_at = [MW](int p) { const int k = p % MW; return (p / MW) % 2 ? MW - 1 - k : k; };
-        for (int p = 0; p < ns; ++p) ++lane_ptr[lane_at(p) + 1];
+        for (int t = 0; t < ns; ++t) ++lane_ptr[lane_of[t] + 1];
         for (int l = 0; l < MW; ++l) lane_ptr[l + 1] += lane_ptr[l];
         lane_slots.resize(ns);
         {
             std::vector<int32_t> fill(lane_ptr.begin(), lane_ptr.end() - 1);
-            for (int p = 0; p < ns; ++p) lane_slots[fill[lane_at(p)]++] = order[p];
+            for (int p = 0; p < ns; ++p) lane_slots[fill[lane_of[order[p]]]++] = order[p];
         }
         cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
         for (int q = 0; q < nq; ++q) {
@@ -506,7 +525,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
                 wq.push_back((int32_t)(stream.size() / 8));
                 size_t len = 0;
                 for (int l = 64 * w; l < 64 * w + 64; ++l) len = std::max(len, lane_ent[l].size());
-                const size_t nb = (len + 7) / 8;
+                const size_t nb = std::max<size_t>(1, (len + 7) / 8);   // the kernel loads one batch at least
                 for (size_t i = 0; i < nb; ++i)
                     for (int l = 64 * w; l < 64 * w + 64; ++l)
                         for (size_t j = 8 * i; j < 8 * i + 8; ++j)
@@ -595,6 +614,22 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     } else {
         p->nchunks = nchunks;
         p->stream_entries = (int64_t)stream.size();
+        // one 32-byte header per block, read with a single scalar load:
+        // first Mat value (lo, hi), Mat values, first cell, cells, chunks,
+        // first (chunk, wave) stream, 0
+        std::vector<int32_t> hdr((size_t)b * 8, 0);
+        for (int32_t i = 0; i < b; ++i) {
+            int32_t *hd = &hdr[(size_t)i * 8];
+            const int64_t s0 = hrp[blk_row0[i]];
+            hd[0] = (int32_t)(uint32_t)(s0 & 0xffffffff);
+            hd[1] = (int32_t)(s0 >> 32);
+            hd[2] = (int32_t)(hrp[blk_row0[i + 1]] - s0);
+            hd[3] = blk_cptr[i];
+            hd[4] = blk_cptr[i + 1] - blk_cptr[i];
+            hd[5] = (blk_w[i + 1] - blk_w[i]) / 8;
+            hd[6] = blk_w[i];
+        }
+        if (e == hipSuccess) e = upload(&p->blk_hdr, hdr, &p->bytes, s);
         if (e == hipSuccess) e = upload(&p->blk_w, blk_w, &p->bytes, s);
         if (e == hipSuccess) e = upload(&p->wq, wq, &p->bytes, s);
         if (e == hipSuccess) e = upload(&p->pstream, stream, &p->bytes, s);
@@ -671,6 +706,7 @@ fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const f
     a.row_ptr = A->sp->row_ptr;
     a.out = A->values;
     a.inc = acc == FEM_INC;
+    a.num_cus = ctx->num_cus;
     hipError_t e = femk::launch_mat(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "assemble_mat launch");
     return FEM_OK;

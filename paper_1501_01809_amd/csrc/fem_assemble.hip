@@ -26,6 +26,9 @@ namespace femk {
 namespace {
 
 
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // Everything a kernel reads, by value: device pointers and scalars only.
 struct KArgs {
     const int32_t *__restrict__ blk_row0;
@@ -34,9 +37,10 @@ struct KArgs {
     const int32_t *__restrict__ bverts;
     const int32_t *__restrict__ inc_ptr;
     const uint16_t *__restrict__ ent;
+    const int32_t *__restrict__ blk_hdr;
     const int32_t *__restrict__ blk_w;
     const int32_t *__restrict__ wq;
-    const uint4 *__restrict__ pstream;
+    const uint32_t *__restrict__ pstream;   // 16-byte batches
     const int64_t *__restrict__ row_ptr;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
@@ -53,7 +57,7 @@ KArgs kargs(const AsmArgs &a)
     KArgs k;
     k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts;
     k.inc_ptr = p.inc_ptr; k.ent = p.ent;
-    k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint4 *>(p.pstream);
+    k.blk_hdr = p.blk_hdr; k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint32_t *>(p.pstream);
     k.row_ptr = a.row_ptr; k.coords = a.coords;
     k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
@@ -78,6 +82,17 @@ __device__ __forceinline__ void lds_barrier()
 __device__ __forceinline__ void wait_loads()
 {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Plan arrays are never written by a kernel.  Reading them through the
+// constant address space lets the compiler use scalar loads for uniform
+// addresses; their waits count on lgkmcnt instead of vmcnt, which on gfx9
+// also counts stores and outstanding prefetches (a vector load of a block
+// header would otherwise drain every load and store in flight).
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
 }
 
 // ---------------------------------------------------------------- geometry
@@ -156,8 +171,8 @@ template <> struct Geo<3> {
 constexpr int MWG = 512;
 constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CCH = 2048, LPC = 1; };
-template <> struct MatCfg<3, 1> { static constexpr int CCH = 1536, LPC = 1; };
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1; };
 template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1; };
 template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2; };
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4; };
@@ -244,6 +259,34 @@ __device__ __forceinline__ void issue_verts(const int32_t *__restrict__ bverts, 
     }
 }
 
+// Vertex ids of one cell kept as one register tuple (a tetrahedron's four
+// ids are one 16-byte load), so that a prefetched copy is not split over
+// registers that the compiler would have to fill as soon as it arrives.
+template <int D> struct VIds;
+template <> struct VIds<3> {
+    i32x4 q;
+    __device__ __forceinline__ void load(const int32_t *__restrict__ bverts, int visit)
+    {
+        q = *reinterpret_cast<const i32x4 *>(bverts + (int64_t)visit * 4);
+    }
+    __device__ __forceinline__ void hold() { asm volatile("" : "+v"(q)); }
+    __device__ __forceinline__ void get(int32_t (&v)[4]) const { v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w; }
+};
+template <> struct VIds<2> {
+    int32_t q[3];
+    __device__ __forceinline__ void load(const int32_t *__restrict__ bverts, int visit)
+    {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) q[m] = bverts[(int64_t)visit * 3 + m];
+    }
+    __device__ __forceinline__ void hold()
+    {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) asm volatile("" : "+v"(q[m]));
+    }
+    __device__ __forceinline__ void get(int32_t (&v)[3]) const { v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; }
+};
+
 template <int D>
 __device__ __forceinline__ void issue_coords(const int32_t (&v)[D + 1], const double *__restrict__ X,
                                              const double *__restrict__ coef, CellIn<D> &c)
@@ -279,105 +322,254 @@ __device__ __forceinline__ void mat_part(int part, const double *P, double madet
     }
 }
 
-// One batch of 8 stream indices of a lane.  Index i < SCAP opens Mat value i:
-// the running sum restarts from the value LDS holds there; any other index
-// adds the LDS double it names.  The running sum is stored back after every
-// index, so the open value always holds the lane's latest partial sum (no
-// separate flush).  All 8 loads are issued first: the value an opening index
-// reads is never written earlier in the same batch (a lane opens each value
-// once per chunk, and writes only the value it has open).
+// One batch of 8 stream indices of a lane.  The lane keeps the running sum
+// of the Mat value it has open in registers (acc, its LDS byte address in
+// cur).  Index i < SCAP opens Mat value i: the open value is written back
+// and the running sum restarts from what LDS holds at i (-0.0 the first
+// time, a partial sum from an earlier chunk otherwise); any other index adds
+// the LDS double it names.  All 8 loads are issued first: an opened value is
+// never written earlier in the same batch (a lane opens each value once per
+// chunk, and writes only values it has open).
 template <int SCAP>
-__device__ __forceinline__ void pull_batch(const uint4 w, double *lds, uint32_t &cur, double &acc)
+__device__ __forceinline__ void pull_batch(const u32x4 w, char *lds, uint32_t &cur, double &acc)
 {
     const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
-    uint32_t idx[8];
+    uint32_t ad[8];
     double v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        idx[j] = (j & 1) ? (wd[j >> 1] >> 16) : (wd[j >> 1] & 0xffffu);
-        v[j] = lds[idx[j]];
+        ad[j] = ((j & 1) ? (wd[j >> 1] >> 16) : (wd[j >> 1] & 0xffffu)) << 3;   // byte address
+        v[j] = *reinterpret_cast<const double *>(lds + ad[j]);
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const bool open = idx[j] < (uint32_t)SCAP;
+        const bool open = ad[j] < (uint32_t)SCAP * 8u;
         const double sum = acc + v[j];
+        if (open) *reinterpret_cast<double *>(lds + cur) = acc;
+        cur = open ? ad[j] : cur;
         acc = open ? v[j] : sum;
-        cur = open ? idx[j] : cur;
-        lds[cur] = acc;
     }
 }
 
-// One workgroup per row block:
-//   set the block's Mat values to -0.0 (the identity of the sums);
-//   per chunk of cells: issue the lane's first stream batches, gather the
-//     cells, compute their element tensors into LDS, barrier, walk the
-//     stream, barrier;
-//   write the block's values out (one contiguous, coalesced range).
+// Uniform description of one row block: the plan's 32-byte header, one
+// scalar load.  [0..1] first Mat value, [2] Mat values, [3] first cell,
+// [4] cells, [5] chunks, [6] first (chunk, wave) stream.
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+struct MatBlk {
+    i32x8 v;
+    __device__ __forceinline__ int64_t s0() const { return (int64_t)(((uint64_t)(uint32_t)v[1] << 32) | (uint32_t)v[0]); }
+    __device__ __forceinline__ int ns() const { return v[2]; }
+    __device__ __forceinline__ int c0() const { return v[3]; }
+    __device__ __forceinline__ int nc() const { return v[4]; }
+    __device__ __forceinline__ int nq() const { return v[5]; }
+    __device__ __forceinline__ int w0() const { return v[6]; }
+};
+
+__device__ __forceinline__ MatBlk mat_blk(const KArgs &a, int b)
+{
+    MatBlk h;
+    h.v = ldc(reinterpret_cast<const i32x8 *>(a.blk_hdr) + b);
+    return h;
+}
+
+// Keeps the compiler from consuming a prefetched register before this point
+// (it would otherwise hoist address arithmetic next to the load and wait for
+// the load right there).
+template <typename T>
+__device__ __forceinline__ void hold(T &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
+// Walks the lane's stream of one (chunk, wave): the first NBMAX batches were
+// loaded into sv ahead of time (every stream has at least one batch), rare
+// longer streams load the rest one batch at a time.  Ends by writing back
+// the value left open.
+template <int SCAP, int ZIDX>
+__device__ __forceinline__ void pull_stream(u32x4 (&sv)[NBMAX], const u32x4 *__restrict__ ps, int nb,
+                                            double *lds)
+{
+    char *lb = reinterpret_cast<char *>(lds);
+    uint32_t cur = (uint32_t)ZIDX * 8u;   // until the first open: ZIDX, which keeps -0.0
+    double acc = -0.0;
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i)
+        if (i < nb) pull_batch<SCAP>(sv[i], lb, cur, acc);
+    for (int i = NBMAX; i < nb; ++i) pull_batch<SCAP>(ps[(int64_t)i * 64], lb, cur, acc);
+    *reinterpret_cast<double *>(lb + cur) = acc;
+}
+
+// Waits for every prefetched stream batch at once (they were issued before
+// the chunk's element tensors were computed, so they have long arrived).
+// Done before any younger prefetch is issued, the stream walk then waits for
+// nothing (waits count loads in issue order).
+__device__ __forceinline__ void hold_stream(u32x4 (&sv)[NBMAX])
+{
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) asm volatile("" : "+v"(sv[i]));
+}
+
+__device__ __forceinline__ void load_stream(u32x4 (&sv)[NBMAX], const u32x4 *__restrict__ ps, int nb)
+{
+#pragma unroll
+    for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(i < nb ? i : nb - 1) * 64];
+}
+
+// Stream of chunk q of a block, for this wave.
+__device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, int q, int wave, int lane, int &nb,
+                                             const u32x4 *__restrict__ &ps)
+{
+    const int st = ldc(a.wq + h.w0() + 8 * q + wave);
+    nb = (ldc(a.wq + h.w0() + 8 * q + wave + 1) - st) >> 6;
+    ps = reinterpret_cast<const u32x4 *>(a.pstream) + st + lane;
+}
+
+// Persistent: one workgroup per CU walks a contiguous range of row blocks
+// (the workgroups of one XCD, launch index mod 8, take one contiguous eighth
+// of the blocks, so neighbouring blocks share that XCD's L2).  Software
+// pipeline over the blocks: the headers of block b+2, the stream offsets,
+// first-chunk stream batches, vertex ids and coordinates of block b+1 are
+// all in flight while block b computes and walks its stream.  Per block:
+//   first chunk: issue the next block's vertex ids; compute the element
+//     tensors into LDS (cell data gathered during the previous block);
+//     barrier; (last chunk) issue the next block's coordinates; walk the
+//     stream; (last chunk) issue the next block's first stream batches;
+//     barrier;
+//   further chunks (rare: a row meeting more cells than a chunk holds): the
+//     same with the chunk's data gathered on the spot;
+//   write the block's Mat values out (one contiguous, coalesced range) and
+//   reset the value area to -0.0, the identity of the sums, for the next
+//   block (each lane touches the same LDS values in both loops).
+// The common path has no branch around a global load, and every prefetched
+// register is consumed before a younger load is waited for, so the
+// compiler's waits stay exact and never drain the prefetches.
 template <int D, int K>
-__global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a)
+__global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
 {
     using T = typename TabOf<D, K>::T;
     using L = MatLds<D, K>;
     constexpr int NE = T::NE, CCH = L::CCH, LPC = MatCfg<D, K>::LPC;
     constexpr int NP = (D + 1) * Geo<D>::NM;
-    constexpr int ITEMS = CCH * LPC;
-    constexpr int PASSES = (ITEMS + MWG - 1) / MWG;
+    constexpr int CO = 4;         // Mat values per lane and round of the write-out
+    static_assert(CCH * LPC <= MWG, "one cell item per lane");
     static_assert(T::NG % LPC == 0, "groups per lane");
     __shared__ double lds[L::TOTAL];
 
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
-    const int64_t s0 = a.row_ptr[r0];
-    const int ns = (int)(a.row_ptr[r1] - s0);
-    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
-    const int w0 = a.blk_w[b], nq = (a.blk_w[b + 1] - w0) >> 3;
-    for (int s = tid; s < ns; s += MWG) lds[s] = -0.0;
+    const int lcc = tid % CCH, part = tid / CCH;
+    const bool has_item = tid < CCH * LPC;
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int rank = G % 8 == 0 ? (bid % 8) * (G / 8) + bid / 8 : bid;
+    const int bb = (int)((int64_t)nblk * rank / G), be = (int)((int64_t)nblk * (rank + 1) / G);
+    if (bb >= be) return;
+    double *__restrict__ E = lds + L::SCAP + lcc * NE;
+
+    MatBlk h = mat_blk(a, bb);
+    MatBlk hn = bb + 1 < be ? mat_blk(a, bb + 1) : h;
+    int nb = 0;
+    const u32x4 *__restrict__ ps = nullptr;
+    u32x4 sv[NBMAX];             // first-chunk stream batches of the current block
+    CellIn<D> cin;               // first-chunk cell data of the current block
+    VIds<D> vn;                  // vertex ids of the next block's first-chunk cell
+    if (h.nq() > 0) {
+        chunk_stream(a, h, 0, wave, lane, nb, ps);
+        load_stream(sv, ps, nb);
+    }
+    if (has_item && lcc < h.nc()) {
+        int32_t v[D + 1];
+        issue_verts<D>(a.bverts, h.c0() + lcc, v);
+        issue_coords<D>(v, a.coords, a.coeff, cin);
+    }
+    for (int s = tid; s < h.ns(); s += MWG) lds[s] = -0.0;
     if (tid == 0) lds[L::ZIDX] = -0.0;
 
-    uint32_t cur = L::ZIDX;    // writes before the first open go to ZIDX and store -0.0 there
-    double acc = -0.0;
-    for (int q = 0; q < nq; ++q) {
-        const int st = a.wq[w0 + 8 * q + wave];
-        const int nb = (a.wq[w0 + 8 * q + wave + 1] - st) >> 6;
-        const uint4 *__restrict__ ps = a.pstream + st + lane;
-        uint4 sv[NBMAX];
-        if (nb > 0) {
-#pragma unroll
-            for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(i < nb ? i : nb - 1) * 64];
-        }
-#pragma unroll
-        for (int pass = 0; pass < PASSES; ++pass) {
-            const int item = tid + pass * MWG;
-            const int lcc = item % CCH, part = item / CCH;
-            const int lc = q * CCH + lcc;
-            if (item < ITEMS && lc < nc) {
-                int32_t v[D + 1];
-                CellIn<D> cin;
-                issue_verts<D>(a.bverts, c0 + lc, v);
-                issue_coords<D>(v, a.coords, a.coeff, cin);
+    for (int b = bb; b < be; ++b) {
+        const bool more = b + 1 < be;
+        const MatBlk hnn = b + 2 < be ? mat_blk(a, b + 2) : hn;
+        int nbn = 0;
+        const u32x4 *__restrict__ psn = ps;
+        if (more && hn.nq() > 0) chunk_stream(a, hn, 0, wave, lane, nbn, psn);
+        // prefetch for the next block (uniform; lanes past its cells load a
+        // duplicate of its last cell, unused)
+        const bool pf = more && hn.nc() > 0;
+        const int vnext = hn.c0() + (lcc < hn.nc() ? lcc : hn.nc() - 1);
+        if (h.nq() > 0) {
+            if (pf) vn.load(a.bverts, vnext);
+            if (has_item && lcc < h.nc()) {
                 double P[NP], madet;
                 tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
-                mat_part<T, LPC>(part, P, madet, lds + L::SCAP + lcc * NE);
+                mat_part<T, LPC>(part, P, madet, E);
+            }
+            lds_barrier();
+            hold_stream(sv);
+            if (h.nq() == 1 && pf) {
+                int32_t v[D + 1];
+                vn.hold();
+                vn.get(v);
+                issue_coords<D>(v, a.coords, a.coeff, cin);
+            }
+            pull_stream<L::SCAP, L::ZIDX>(sv, ps, nb, lds);
+            if (h.nq() == 1 && more && hn.nq() > 0) load_stream(sv, psn, nbn);
+            lds_barrier();
+        }
+        for (int q = 1; q < h.nq(); ++q) {
+            const int lc = q * CCH + lcc;
+            if (has_item && lc < h.nc()) {
+                int32_t v[D + 1];
+                CellIn<D> cq;
+                issue_verts<D>(a.bverts, h.c0() + lc, v);
+                issue_coords<D>(v, a.coords, a.coeff, cq);
+                double P[NP], madet;
+                tensor_inputs<D>(cq, a.cstiff, a.cmass, P, &madet);
+                mat_part<T, LPC>(part, P, madet, E);
+            }
+            int nbq;
+            const u32x4 *__restrict__ psq;
+            chunk_stream(a, h, q, wave, lane, nbq, psq);
+            u32x4 svq[NBMAX];
+            load_stream(svq, psq, nbq);
+            lds_barrier();
+            hold_stream(svq);
+            if (q == h.nq() - 1 && pf) {
+                int32_t v[D + 1];
+                vn.hold();
+                vn.get(v);
+                issue_coords<D>(v, a.coords, a.coeff, cin);
+            }
+            pull_stream<L::SCAP, L::ZIDX>(svq, psq, nbq, lds);
+            if (q == h.nq() - 1 && more && hn.nq() > 0) load_stream(sv, psn, nbn);
+            lds_barrier();
+        }
+        if (h.nq() == 0) {
+            if (pf) {
+                int32_t v[D + 1];
+                issue_verts<D>(a.bverts, vnext, v);
+                issue_coords<D>(v, a.coords, a.coeff, cin);
+            }
+            if (more && hn.nq() > 0) load_stream(sv, psn, nbn);
+        }
+        // write-out: CO values per lane in flight at once
+        double *__restrict__ out = a.out + h.s0();
+        for (int s0 = tid; s0 < h.ns(); s0 += CO * MWG) {
+            double t[CO];
+#pragma unroll
+            for (int k = 0; k < CO; ++k) t[k] = s0 + k * MWG < h.ns() ? lds[s0 + k * MWG] : 0.0;
+            if (a.inc) {
+#pragma unroll
+                for (int k = 0; k < CO; ++k)
+                    if (s0 + k * MWG < h.ns()) out[s0 + k * MWG] += t[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < CO; ++k)
+                    if (s0 + k * MWG < h.ns()) out[s0 + k * MWG] = t[k];
             }
         }
-        lds_barrier();
-        for (int g = 0; g < nb; g += NBMAX) {
-            if (g > 0) {
-#pragma unroll
-                for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(g + i < nb ? g + i : nb - 1) * 64];
-            }
-#pragma unroll
-            for (int i = 0; i < NBMAX; ++i)
-                if (g + i < nb) pull_batch<L::SCAP>(sv[i], lds, cur, acc);
-        }
-        lds_barrier();
-    }
-    double *__restrict__ out = a.out + s0;
-    if (a.inc) {
-        for (int s = tid; s < ns; s += MWG) out[s] += lds[s];
-    } else {
-        for (int s = tid; s < ns; s += MWG) out[s] = lds[s];
+        for (int s = tid; s < hn.ns(); s += MWG) lds[s] = -0.0;
+        h = hn;
+        hn = hnn;
+        nb = nbn;
+        ps = psn;
     }
 }
 
@@ -458,7 +650,9 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
 template <int D, int K>
 hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(a.plan->nblk), dim3(MWG), 0, s, kargs(a));
+    const int nblk = a.plan->nblk;
+    const int grid = std::min(nblk, std::max(a.num_cus, 1));
+    hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(grid), dim3(MWG), 0, s, kargs(a), nblk);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct fem_plan {
     int32_t *bverts = nullptr;    // [visits][dim+1] vertex ids of each bcell entry
     int32_t *inc_ptr = nullptr;   // Dat plans: [nrows+1] entry range of each row
     uint16_t *ent = nullptr;      // Dat plans: (local cell << lbits) | local index
+    int32_t *blk_hdr = nullptr;   // Mat plans: [nblk][8] block header (layout in fem_assemble.hip)
     int32_t *blk_w = nullptr;     // Mat plans: [nblk+1] first (chunk, wave) stream of each block
     int32_t *wq = nullptr;        // Mat plans: [streams+1] first uint4 of each (chunk, wave) stream
     uint16_t *pstream = nullptr;  // Mat plans: the streams
@@ -88,6 +89,7 @@ struct AsmArgs {
     const double *x;         // action input
     double *out;             // Mat values / Dat
     int inc;                 // 1: INC, 0: WRITE
+    int num_cus;             // compute units of the device (persistent grids)
 };
 hipError_t launch_mat(const AsmArgs &a, hipStream_t s);
 hipError_t launch_vec(const AsmArgs &a, hipStream_t s);
