@@ -8,6 +8,8 @@ import itertools
 from fractions import Fraction
 from math import factorial
 
+import os
+
 import numpy as np
 import pytest
 
@@ -182,29 +184,44 @@ def _assemble_dense(mesh, deg, kappa, form):
     return A
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """Hand-derived scaled matrices of a fixture file: {form: (scale, matrix)},
+    NaN where the fixture marks a pair absent from the sparsity."""
+    out, cur = {}, None
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("scale"):
+                _, sc, form = line.split()
+                cur = (form, float(sc), [])
+                out[form] = cur
+                continue
+            cur[2].append([np.nan if t == "x" else float(t) for t in line.split()])
+    return {f: (sc, np.array(rows)) for f, (_, sc, rows) in out.items()}
+
+
 def test_two_triangles_hand_values():
     m = fi.two_triangles()
-    K2 = np.array([[2, -1, 0, -1], [-1, 2, -1, 0], [0, -1, 2, -1], [-1, 0, -1, 2]], float)
-    M24 = np.array([[4, 1, 2, 1], [1, 2, 1, np.nan], [2, 1, 4, 1], [1, np.nan, 1, 2]])
+    g = _golden("two_triangles_p1.txt")
     K = _assemble_dense(m, 1, np.ones(4), "laplace")
     M = _assemble_dense(m, 1, np.ones(4), "mass")
-    K2[1, 3] = K2[3, 1] = np.nan           # structurally absent
-    np.testing.assert_allclose(2 * K, K2, atol=1e-14)   # nan positions must match
-    np.testing.assert_allclose(24 * M, M24, atol=1e-14)
+    np.testing.assert_allclose(g["laplace"][0] * K, g["laplace"][1], atol=1e-14)   # nan positions must match
+    np.testing.assert_allclose(g["mass"][0] * M, g["mass"][1], atol=1e-14)
     assert K[0, 2] == 0.0                                # structurally present, value 0
 
 
 def test_two_tets_hand_values():
     m = fi.two_tets()
-    nan = np.nan
-    K12 = np.array([[6, -2, -2, -2, nan], [-2, 5, -1, -1, -1], [-2, -1, 5, -1, -1],
-                    [-2, -1, -1, 5, -1], [nan, -1, -1, -1, 3]])
-    M120 = np.array([[2, 1, 1, 1, nan], [1, 6, 3, 3, 2], [1, 3, 6, 3, 2], [1, 3, 3, 6, 2],
-                     [nan, 2, 2, 2, 4]])
+    g = _golden("two_tets_p1.txt")
     K = _assemble_dense(m, 1, np.ones(5), "laplace")
     M = _assemble_dense(m, 1, np.ones(5), "mass")
-    np.testing.assert_allclose(12 * K, K12, atol=1e-13)
-    np.testing.assert_allclose(120 * M, M120, atol=1e-13)
+    np.testing.assert_allclose(g["laplace"][0] * K, g["laplace"][1], atol=1e-13)
+    np.testing.assert_allclose(g["mass"][0] * M, g["mass"][1], atol=1e-13)
     assert abs(np.nansum(M) - 0.5) < 1e-15
 
 
