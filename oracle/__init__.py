@@ -3,7 +3,8 @@
 A plain, slow, single-threaded FP64 C implementation (``oracle.c``) of what
 the parallel loop computes: the global assembly sums of the Helmholtz-type
 bilinear form, the source linear form and the matrix-free action, with its own
-sparsity.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+sparsity; and the nonlinear residual kappa grad(u).grad(v) + u^3 v - f v with
+its vector-Jacobian products (the adjoint assembly).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The product library never does.
 
 Every function here follows the paper's definition of a parallel loop over
@@ -62,6 +63,12 @@ def lib():
         L.oracle_mat_rows.restype = L64
         L.oracle_vec_rows.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, L64, L64, P, P, P]
         L.oracle_vec_rows.restype = I
+        L.oracle_nl_element.argtypes = [I, P, P, P, P, P, P, P, P, P, P, P]
+        L.oracle_nl_element.restype = I
+        L.oracle_nl_residual.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P]
+        L.oracle_nl_residual.restype = I
+        L.oracle_nl_adjoint.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P, P, P]
+        L.oracle_nl_adjoint.restype = I
         _lib = L
     return _lib
 
@@ -221,3 +228,40 @@ def action_rows(dim, degree, cell_vertex, coords, cell_node, kappa, x, nrows, ro
     if rc:
         raise RuntimeError("oracle action_rows failed")
     return out, absv
+
+
+def nl_element(dim, xv, uv, kv, fv=None, lv=None):
+    """Element residual F, adjoint products gu, gk (P1) and their magnitude scales."""
+    n = dim + 1
+    xv = _c(xv, np.float64); uv = _c(uv, np.float64); kv = _c(kv, np.float64)
+    fv = None if fv is None else _c(fv, np.float64); lv = None if lv is None else _c(lv, np.float64)
+    out = [np.zeros(n) for _ in range(6)]
+    rc = lib().oracle_nl_element(dim, _p(xv), _p(uv), _p(kv), None if fv is None else _p(fv),
+                                 None if lv is None else _p(lv), *[_p(o) for o in out])
+    if rc:
+        raise RuntimeError(f"oracle nl_element failed ({rc})")
+    return out
+
+
+def nl_residual(dim, cell_vertex, coords, cell_node, u, kappa, f, nnodes):
+    """F_i = integral of kappa grad(u).grad(phi_i) + u^3 phi_i - f phi_i (P1 fields on the nodes)."""
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    u = _c(u, np.float64); k = _c(kappa, np.float64); f = _c(f, np.float64)
+    F = np.zeros(nnodes); Fa = np.zeros(nnodes)
+    rc = lib().oracle_nl_residual(dim, cv.shape[0], _p(cv), _p(X), _p(cn), nnodes, _p(u), _p(k), _p(f),
+                                  _p(F), _p(Fa))
+    if rc:
+        raise RuntimeError(f"oracle nl_residual failed ({rc})")
+    return F, Fa
+
+
+def nl_adjoint(dim, cell_vertex, coords, cell_node, u, kappa, lam, nnodes):
+    """lambda^T dF/du and lambda^T dF/dkappa with their magnitude scales."""
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    u = _c(u, np.float64); k = _c(kappa, np.float64); lam = _c(lam, np.float64)
+    gu = np.zeros(nnodes); gua = np.zeros(nnodes); gk = np.zeros(nnodes); gka = np.zeros(nnodes)
+    rc = lib().oracle_nl_adjoint(dim, cv.shape[0], _p(cv), _p(X), _p(cn), nnodes, _p(u), _p(k), _p(lam),
+                                 _p(gu), _p(gua), _p(gk), _p(gka))
+    if rc:
+        raise RuntimeError(f"oracle nl_adjoint failed ({rc})")
+    return gu, gua, gk, gka

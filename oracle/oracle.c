@@ -669,3 +669,137 @@ int oracle_vec_rows(int kind, int dim, int degree, int64_t ncells, const int32_t
     free(slot);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Nonlinear residual and its vector-Jacobian products (P1)             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The residual of the differentiation benchmark,
+ *
+ *   F_i(u, kappa) = integral of  kappa grad(u).grad(phi_i) + u^3 phi_i - f phi_i,
+ *
+ * and, for a vector lambda (a P1 field lambda_h = sum_i lambda_i phi_i), the
+ * vector-Jacobian products
+ *
+ *   (lambda^T dF/du)_j     = integral of  kappa grad(phi_j).grad(lambda_h)
+ *                                         + 3 u^2 phi_j lambda_h,
+ *   (lambda^T dF/dkappa)_k = integral of  phi_k grad(u).grad(lambda_h),
+ *
+ * obtained by differentiating the integrand of F_i with respect to u_j and
+ * kappa_k and contracting with lambda_i.  The adjoint of the residual is what
+ * the paper's closing discussion (adjoint models through the same
+ * abstractions) points to.  u, kappa, f and lambda are P1 fields on the nodes
+ * of the degree-1 space (read through the cell-to-node Map).  The integrand
+ * has degree 4; the rule is exact for it.
+ *
+ * Element level: uv, kv, fv, lv are the nodal values of the cell; any output
+ * may be NULL.  The *_abs outputs sum the magnitudes of the terms.
+ */
+int oracle_nl_element(int dim, const double *xv, const double *uv, const double *kv, const double *fv,
+                      const double *lv, double *F, double *Fabs, double *gu, double *guabs, double *gk,
+                      double *gkabs)
+{
+    const int n = dim + 1;
+    struct rule R;
+    if (make_rule(dim, 4, &R)) return -1;
+    double J[9], Jinv[9];
+    double adet = fabs(cell_geometry(dim, xv, J, Jinv));
+    for (int i = 0; i < n; ++i) {
+        if (F) F[i] = 0.0;
+        if (Fabs) Fabs[i] = 0.0;
+        if (gu) gu[i] = 0.0;
+        if (guabs) guabs[i] = 0.0;
+        if (gk) gk[i] = 0.0;
+        if (gkabs) gkabs[i] = 0.0;
+    }
+    for (int p = 0; p < R.np; ++p) {
+        double lam[4], phi[MAXLOC], gphi[MAXLOC * 3];
+        eval_at_point(dim, 1, xv, Jinv, &R.pts[p * dim], lam, phi, gphi);
+        const double w = R.wts[p] * adet;
+        double uq = 0, ua = 0, kq = 0, ka = 0, fq = 0, fa = 0, lq = 0, la = 0;
+        double gu_[3] = {0, 0, 0}, gl_[3] = {0, 0, 0};
+        for (int m = 0; m < n; ++m) {
+            uq += uv[m] * phi[m]; ua += fabs(uv[m] * phi[m]);
+            kq += kv[m] * phi[m]; ka += fabs(kv[m] * phi[m]);
+            if (fv) { fq += fv[m] * phi[m]; fa += fabs(fv[m] * phi[m]); }
+            if (lv) { lq += lv[m] * phi[m]; la += fabs(lv[m] * phi[m]); }
+            for (int r = 0; r < dim; ++r) {
+                gu_[r] += uv[m] * gphi[m * dim + r];
+                if (lv) gl_[r] += lv[m] * gphi[m * dim + r];
+            }
+        }
+        double gul = 0, gula = 0;
+        for (int r = 0; r < dim; ++r) { gul += gu_[r] * gl_[r]; gula += fabs(gu_[r] * gl_[r]); }
+        for (int i = 0; i < n; ++i) {
+            double gg = 0, gga = 0, gil = 0, gila = 0;
+            for (int r = 0; r < dim; ++r) {
+                gg += gu_[r] * gphi[i * dim + r];
+                gga += fabs(gu_[r] * gphi[i * dim + r]);
+                gil += gphi[i * dim + r] * gl_[r];
+                gila += fabs(gphi[i * dim + r] * gl_[r]);
+            }
+            if (F) F[i] += w * (kq * gg + uq * uq * uq * phi[i] - fq * phi[i]);
+            if (Fabs) Fabs[i] += fabs(w) * (ka * gga + ua * ua * ua * fabs(phi[i]) + fa * fabs(phi[i]));
+            if (gu) gu[i] += w * (kq * gil + 3.0 * uq * uq * phi[i] * lq);
+            if (guabs) guabs[i] += fabs(w) * (ka * gila + 3.0 * ua * ua * fabs(phi[i]) * la);
+            if (gk) gk[i] += w * phi[i] * gul;
+            if (gkabs) gkabs[i] += fabs(w * phi[i]) * gula;
+        }
+    }
+    return 0;
+}
+
+static void gather_nodal(int n, int64_t c, const int32_t *cell_node, const double *a, double *av)
+{
+    for (int i = 0; i < n; ++i) av[i] = a ? a[cell_node[c * n + i]] : 0.0;
+}
+
+/* Global residual F[nnodes] (and its magnitude scale), cells in index order. */
+int oracle_nl_residual(int dim, int64_t ncells, const int32_t *cell_vertex, const double *coords,
+                       const int32_t *cell_node, int64_t nnodes, const double *u, const double *kappa,
+                       const double *f, double *F, double *Fabs)
+{
+    const int n = dim + 1;
+    memset(F, 0, sizeof(double) * nnodes);
+    memset(Fabs, 0, sizeof(double) * nnodes);
+    double xv[12], uv[4], kv[4], fv[4], Fe[4], Fa[4], dummy[4];
+    for (int64_t c = 0; c < ncells; ++c) {
+        gather_cell(dim, c, cell_vertex, coords, NULL, xv, dummy);
+        gather_nodal(n, c, cell_node, u, uv);
+        gather_nodal(n, c, cell_node, kappa, kv);
+        gather_nodal(n, c, cell_node, f, fv);
+        if (oracle_nl_element(dim, xv, uv, kv, fv, NULL, Fe, Fa, NULL, NULL, NULL, NULL)) return -1;
+        for (int i = 0; i < n; ++i) {
+            F[cell_node[c * n + i]] += Fe[i];
+            Fabs[cell_node[c * n + i]] += Fa[i];
+        }
+    }
+    return 0;
+}
+
+/* Global vector-Jacobian products gu = lambda^T dF/du, gk = lambda^T dF/dkappa. */
+int oracle_nl_adjoint(int dim, int64_t ncells, const int32_t *cell_vertex, const double *coords,
+                      const int32_t *cell_node, int64_t nnodes, const double *u, const double *kappa,
+                      const double *lambda, double *gu, double *guabs, double *gk, double *gkabs)
+{
+    const int n = dim + 1;
+    memset(gu, 0, sizeof(double) * nnodes);
+    memset(guabs, 0, sizeof(double) * nnodes);
+    memset(gk, 0, sizeof(double) * nnodes);
+    memset(gkabs, 0, sizeof(double) * nnodes);
+    double xv[12], uv[4], kv[4], lv[4], a[4], aa[4], b[4], ba[4], dummy[4];
+    for (int64_t c = 0; c < ncells; ++c) {
+        gather_cell(dim, c, cell_vertex, coords, NULL, xv, dummy);
+        gather_nodal(n, c, cell_node, u, uv);
+        gather_nodal(n, c, cell_node, kappa, kv);
+        gather_nodal(n, c, cell_node, lambda, lv);
+        if (oracle_nl_element(dim, xv, uv, kv, NULL, lv, NULL, NULL, a, aa, b, ba)) return -1;
+        for (int i = 0; i < n; ++i) {
+            const int32_t r = cell_node[c * n + i];
+            gu[r] += a[i]; guabs[r] += aa[i];
+            gk[r] += b[i]; gkabs[r] += ba[i];
+        }
+    }
+    return 0;
+}
