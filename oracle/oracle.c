@@ -696,13 +696,11 @@ int oracle_vec_rows(int kind, int dim, int degree, int64_t ncells, const int32_t
  * Element level: uv, kv, fv, lv are the nodal values of the cell; any output
  * may be NULL.  The *_abs outputs sum the magnitudes of the terms.
  */
-int oracle_nl_element(int dim, const double *xv, const double *uv, const double *kv, const double *fv,
-                      const double *lv, double *F, double *Fabs, double *gu, double *guabs, double *gk,
-                      double *gkabs)
+static void nl_element_rule(int dim, const struct rule *R, const double *xv, const double *uv,
+                            const double *kv, const double *fv, const double *lv, double *F, double *Fabs,
+                            double *gu, double *guabs, double *gk, double *gkabs)
 {
     const int n = dim + 1;
-    struct rule R;
-    if (make_rule(dim, 4, &R)) return -1;
     double J[9], Jinv[9];
     double adet = fabs(cell_geometry(dim, xv, J, Jinv));
     for (int i = 0; i < n; ++i) {
@@ -713,10 +711,10 @@ int oracle_nl_element(int dim, const double *xv, const double *uv, const double 
         if (gk) gk[i] = 0.0;
         if (gkabs) gkabs[i] = 0.0;
     }
-    for (int p = 0; p < R.np; ++p) {
+    for (int p = 0; p < R->np; ++p) {
         double lam[4], phi[MAXLOC], gphi[MAXLOC * 3];
-        eval_at_point(dim, 1, xv, Jinv, &R.pts[p * dim], lam, phi, gphi);
-        const double w = R.wts[p] * adet;
+        eval_at_point(dim, 1, xv, Jinv, &R->pts[p * dim], lam, phi, gphi);
+        const double w = R->wts[p] * adet;
         double uq = 0, ua = 0, kq = 0, ka = 0, fq = 0, fa = 0, lq = 0, la = 0;
         double gu_[3] = {0, 0, 0}, gl_[3] = {0, 0, 0};
         for (int m = 0; m < n; ++m) {
@@ -747,6 +745,15 @@ int oracle_nl_element(int dim, const double *xv, const double *uv, const double 
             if (gkabs) gkabs[i] += fabs(w * phi[i]) * gula;
         }
     }
+}
+
+int oracle_nl_element(int dim, const double *xv, const double *uv, const double *kv, const double *fv,
+                      const double *lv, double *F, double *Fabs, double *gu, double *guabs, double *gk,
+                      double *gkabs)
+{
+    struct rule R;
+    if (make_rule(dim, 4, &R)) return -1;
+    nl_element_rule(dim, &R, xv, uv, kv, fv, lv, F, Fabs, gu, guabs, gk, gkabs);
     return 0;
 }
 
@@ -764,12 +771,14 @@ int oracle_nl_residual(int dim, int64_t ncells, const int32_t *cell_vertex, cons
     memset(F, 0, sizeof(double) * nnodes);
     memset(Fabs, 0, sizeof(double) * nnodes);
     double xv[12], uv[4], kv[4], fv[4], Fe[4], Fa[4], dummy[4];
+    struct rule R;
+    if (make_rule(dim, 4, &R)) return -1;
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, NULL, xv, dummy);
         gather_nodal(n, c, cell_node, u, uv);
         gather_nodal(n, c, cell_node, kappa, kv);
         gather_nodal(n, c, cell_node, f, fv);
-        if (oracle_nl_element(dim, xv, uv, kv, fv, NULL, Fe, Fa, NULL, NULL, NULL, NULL)) return -1;
+        nl_element_rule(dim, &R, xv, uv, kv, fv, NULL, Fe, Fa, NULL, NULL, NULL, NULL);
         for (int i = 0; i < n; ++i) {
             F[cell_node[c * n + i]] += Fe[i];
             Fabs[cell_node[c * n + i]] += Fa[i];
@@ -789,12 +798,14 @@ int oracle_nl_adjoint(int dim, int64_t ncells, const int32_t *cell_vertex, const
     memset(gk, 0, sizeof(double) * nnodes);
     memset(gkabs, 0, sizeof(double) * nnodes);
     double xv[12], uv[4], kv[4], lv[4], a[4], aa[4], b[4], ba[4], dummy[4];
+    struct rule R;
+    if (make_rule(dim, 4, &R)) return -1;
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, NULL, xv, dummy);
         gather_nodal(n, c, cell_node, u, uv);
         gather_nodal(n, c, cell_node, kappa, kv);
         gather_nodal(n, c, cell_node, lambda, lv);
-        if (oracle_nl_element(dim, xv, uv, kv, NULL, lv, NULL, NULL, a, aa, b, ba)) return -1;
+        nl_element_rule(dim, &R, xv, uv, kv, NULL, lv, NULL, NULL, a, aa, b, ba);
         for (int i = 0; i < n; ++i) {
             const int32_t r = cell_node[c * n + i];
             gu[r] += a[i]; guabs[r] += aa[i];
