@@ -26,6 +26,10 @@
  *   FEM_LAPLACE    kappa grad(u).grad(v)
  *   FEM_MASS       u v
  *   FEM_SOURCE     f v              (linear form)
+ *   FEM_NL_RESIDUAL  kappa grad(u).grad(v) + u^3 v - f v   (nonlinear residual,
+ *                  P1 only; u, kappa, f are P1 fields on the nodes; its
+ *                  vector-Jacobian products come from
+ *                  fem_par_loop_assemble_adjoint)
  *
  * Memory, ownership, ordering
  *   - Every pointer inside fem_map, fem_dat, fem_sparsity and fem_mat is a
@@ -86,12 +90,14 @@ typedef enum fem_access { FEM_READ = 0, FEM_WRITE = 1, FEM_INC = 2 } fem_access;
 
 typedef enum fem_cell { FEM_TRIANGLE = 2, FEM_TETRAHEDRON = 3 } fem_cell;
 
-/* Arithmetic of the element contraction.  FEM_FP64 is the only one provided
- * by this version; the others return FEM_E_UNSUPPORTED. */
+/* Arithmetic of the local kernel.  FEM_FP64 everywhere; FEM_FP32 for
+ * FEM_NL_RESIDUAL (its residual and adjoint: geometry, element values and
+ * the per-row sums in binary32, results stored as float64); the others
+ * return FEM_E_UNSUPPORTED. */
 typedef enum fem_prec { FEM_FP64 = 0, FEM_FP32 = 1, FEM_BF16 = 2, FEM_FP16 = 3 } fem_prec;
 
 typedef enum fem_kind {
-    FEM_MASS = 0, FEM_LAPLACE = 1, FEM_HELMHOLTZ = 2, FEM_SOURCE = 3
+    FEM_MASS = 0, FEM_LAPLACE = 1, FEM_HELMHOLTZ = 2, FEM_SOURCE = 3, FEM_NL_RESIDUAL = 4
 } fem_kind;
 
 /* A Set: only a size ("Sets"). */
@@ -142,9 +148,12 @@ typedef struct fem_form {
 
 /* par_loop data arguments other than the output: the iteration Set (cells),
  * the coordinate field (a P1 vector Dat read through cell_vertex), the
- * cell-to-node Map of the P_k space, and P1 coefficient Dats read through
- * cell_vertex: coeff[0] is kappa for the bilinear forms and f for
- * FEM_SOURCE. */
+ * cell-to-node Map of the P_k space, and coefficient Dats.  For the linear
+ * and bilinear forms they are P1 fields read through cell_vertex: coeff[0]
+ * is kappa for the bilinear forms and f for FEM_SOURCE.  For
+ * FEM_NL_RESIDUAL they are fields of the P1 space itself, on the node Set,
+ * read through cell_node: coeff[0] = u, coeff[1] = kappa, coeff[2] = f (f is
+ * not read by the adjoint). */
 typedef struct fem_args {
     const fem_set *cells;
     const fem_map *cell_vertex;
@@ -212,9 +221,29 @@ fem_status fem_plan_info(const fem_plan *plan, int64_t *nblocks, int64_t *cell_v
 fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
                                      const fem_args *args, fem_mat *A, fem_access acc);
 
-/* b[cell_node(c,i)] (+)= integral over cell c of f v_i (FEM_SOURCE form). */
+/* b[cell_node(c,i)] (+)= integral over cell c of the linear form: f v_i
+ * (FEM_SOURCE) or the residual kappa grad(u).grad(v_i) + u^3 v_i - f v_i
+ * (FEM_NL_RESIDUAL). */
 fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
                                      const fem_args *args, fem_dat *b, fem_access acc);
+
+/*
+ * Adjoint (vector-Jacobian product) assembly of the FEM_NL_RESIDUAL residual
+ * F(u, kappa): for a P1 field lambda on the nodes,
+ *   g_u[j]     (+)= sum_i lambda_i dF_i/du_j
+ *               = sum over cells of integral of kappa grad(v_j).grad(lambda)
+ *                                             + 3 u^2 v_j lambda,
+ *   g_kappa[k] (+)= sum_i lambda_i dF_i/dkappa_k
+ *               = sum over cells of integral of v_k grad(u).grad(lambda),
+ * assembled like a Dat (the reverse mode of the residual; the paper's closing
+ * discussion of adjoints through the same abstractions).  args as for the
+ * residual (coeff[0] = u, coeff[1] = kappa); lambda, g_u, g_kappa are Dats on
+ * the node Set; either output may be NULL.  Plan: a Dat plan (sp == NULL).
+ * Asynchronous; allocates nothing.
+ */
+fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                         const fem_args *args, const fem_dat *lambda, fem_dat *g_u,
+                                         fem_dat *g_kappa, fem_access acc);
 
 /* Matrix-free action y (+)= A x with A the assembled bilinear form, computed
  * cell by cell without forming the CSR matrix (the paper's wave benchmark

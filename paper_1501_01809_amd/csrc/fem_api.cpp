@@ -74,10 +74,13 @@ fem_status check_form(fem_ctx *ctx, const fem_form *f)
     if (f->degree < 1 || f->degree > 3)
         return fail(ctx, FEM_E_UNSUPPORTED, "degree %d not supported (1..3)", f->degree);
     if (f->dim != 1) return fail(ctx, FEM_E_UNSUPPORTED, "value dimension %d not supported", f->dim);
-    if (f->prec != FEM_FP64)
-        return fail(ctx, FEM_E_UNSUPPORTED, "precision %d not supported", (int)f->prec);
-    if (f->kind < FEM_MASS || f->kind > FEM_SOURCE)
+    if (f->kind < FEM_MASS || f->kind > FEM_NL_RESIDUAL)
         return fail(ctx, FEM_E_UNSUPPORTED, "form kind %d not supported", (int)f->kind);
+    if (f->kind == FEM_NL_RESIDUAL && f->degree != 1)
+        return fail(ctx, FEM_E_UNSUPPORTED, "the nonlinear residual is provided for P1 only");
+    if (!(f->prec == FEM_FP64 || (f->prec == FEM_FP32 && f->kind == FEM_NL_RESIDUAL)))
+        return fail(ctx, FEM_E_UNSUPPORTED, "precision %d not supported for form kind %d", (int)f->prec,
+                    (int)f->kind);
     return FEM_OK;
 }
 
@@ -344,7 +347,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     if (is_mat) {
         if (!sp->row_ptr || sp->nrows != nrows || sp->ncols != nrows || (!sp->col_idx && sp->nnz > 0))
             return fail(ctx, FEM_E_ARG, "plan_create: sparsity does not match the cell_node Map");
-        if (form->kind == FEM_SOURCE)
+        if (form->kind == FEM_SOURCE || form->kind == FEM_NL_RESIDUAL)
             return fail(ctx, FEM_E_ARG, "plan_create: a Mat plan needs a bilinear form");
     }
     femk::Limits lim;
@@ -675,6 +678,17 @@ static fem_status check_plan(fem_ctx *ctx, const fem_plan *plan, const fem_form 
     return FEM_OK;
 }
 
+// The nonlinear residual's fields u, kappa (, f): scalar Dats on the node Set.
+static fem_status check_nodal(fem_ctx *ctx, const fem_args *args, int need)
+{
+    if (args->ncoeff < need)
+        return fail(ctx, FEM_E_ARG, "args: the nonlinear residual needs %d coefficient Dats", need);
+    for (int i = 0; i < need; ++i)
+        if (!dat_ok(args->coeff[i], args->cell_node->to, 1))
+            return fail(ctx, FEM_E_ARG, "args: coeff[%d] must be a scalar Dat on the node Set", i);
+    return FEM_OK;
+}
+
 static femk::AsmArgs base_args(const fem_plan *plan, const fem_args *args)
 {
     femk::AsmArgs a{};
@@ -691,7 +705,8 @@ fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const f
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
-    if (form->kind == FEM_SOURCE) return fail(ctx, FEM_E_ARG, "assemble_mat needs a bilinear form");
+    if (form->kind == FEM_SOURCE || form->kind == FEM_NL_RESIDUAL)
+        return fail(ctx, FEM_E_ARG, "assemble_mat needs a bilinear form");
     const bool need_k = form->kind != FEM_MASS;
     if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
     if ((st = check_plan(ctx, plan, form, args, true)) != FEM_OK) return st;
@@ -718,7 +733,25 @@ fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const f
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
-    if (form->kind != FEM_SOURCE) return fail(ctx, FEM_E_ARG, "assemble_vec needs FEM_SOURCE");
+    if (form->kind != FEM_SOURCE && form->kind != FEM_NL_RESIDUAL)
+        return fail(ctx, FEM_E_ARG, "assemble_vec needs FEM_SOURCE or FEM_NL_RESIDUAL");
+    if (form->kind == FEM_NL_RESIDUAL) {
+        if ((st = check_args(ctx, form, args, false)) != FEM_OK) return st;
+        if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
+        if ((st = check_nodal(ctx, args, 3)) != FEM_OK) return st;
+        if (!dat_ok(b, args->cell_node->to, 1))
+            return fail(ctx, FEM_E_ARG, "assemble_vec: b must be a Dat on the nodes");
+        if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
+        femk::AsmArgs a = base_args(plan, args);
+        a.x = args->coeff[0]->data;
+        a.coeff = args->coeff[1]->data;
+        a.aux = args->coeff[2]->data;
+        a.out = b->data;
+        a.inc = acc == FEM_INC;
+        hipError_t e = femk::launch_nl(a, 0, form->prec == FEM_FP32, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_vec launch");
+        return FEM_OK;
+    }
     if ((st = check_args(ctx, form, args, true)) != FEM_OK) return st;
     if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
     if (!dat_ok(b, args->cell_node->to, 1)) return fail(ctx, FEM_E_ARG, "assemble_vec: b must be a Dat on the nodes");
@@ -738,7 +771,8 @@ fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
-    if (form->kind == FEM_SOURCE) return fail(ctx, FEM_E_ARG, "apply_action needs a bilinear form");
+    if (form->kind == FEM_SOURCE || form->kind == FEM_NL_RESIDUAL)
+        return fail(ctx, FEM_E_ARG, "apply_action needs a bilinear form");
     const bool need_k = form->kind != FEM_MASS;
     if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
     if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
@@ -754,6 +788,47 @@ fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *
     a.inc = acc == FEM_INC;
     hipError_t e = femk::launch_action(a, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "apply_action launch");
+    return FEM_OK;
+}
+
+fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                         const fem_args *args, const fem_dat *lambda, fem_dat *g_u,
+                                         fem_dat *g_kappa, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (form->kind != FEM_NL_RESIDUAL) return fail(ctx, FEM_E_ARG, "assemble_adjoint needs FEM_NL_RESIDUAL");
+    if ((st = check_args(ctx, form, args, false)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
+    if ((st = check_nodal(ctx, args, 2)) != FEM_OK) return st;
+    const fem_set *nodes = args->cell_node->to;
+    if (!dat_ok(lambda, nodes, 1)) return fail(ctx, FEM_E_ARG, "assemble_adjoint: lambda must be a Dat on the nodes");
+    if ((g_u && !dat_ok(g_u, nodes, 1)) || (g_kappa && !dat_ok(g_kappa, nodes, 1)))
+        return fail(ctx, FEM_E_ARG, "assemble_adjoint: outputs must be Dats on the nodes");
+    if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
+    for (const fem_dat *o : {(const fem_dat *)g_u, (const fem_dat *)g_kappa})
+        if (o && nodes->size > 0 && (o->data == lambda->data || o->data == args->coeff[0]->data ||
+                                     o->data == args->coeff[1]->data))
+            return fail(ctx, FEM_E_ARG, "assemble_adjoint: an output aliases an input");
+    if (g_u && g_kappa && g_u->data == g_kappa->data && nodes->size > 0)
+        return fail(ctx, FEM_E_ARG, "assemble_adjoint: g_u and g_kappa alias");
+    femk::AsmArgs a = base_args(plan, args);
+    a.x = args->coeff[0]->data;
+    a.coeff = args->coeff[1]->data;
+    a.aux = lambda->data;
+    a.inc = acc == FEM_INC;
+    const bool fp32 = form->prec == FEM_FP32;
+    if (g_u) {
+        a.out = g_u->data;
+        hipError_t e = femk::launch_nl(a, 1, fp32, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
+    }
+    if (g_kappa) {
+        a.out = g_kappa->data;
+        hipError_t e = femk::launch_nl(a, 2, fp32, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
+    }
     return FEM_OK;
 }
 

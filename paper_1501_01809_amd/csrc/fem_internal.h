@@ -86,7 +86,8 @@ struct AsmArgs {
     const double *coeff;     // kappa (bilinear) or f (source)
     double cstiff, cmass;
     const int64_t *row_ptr;
-    const double *x;         // action input
+    const double *x;         // action input; u of the nonlinear residual
+    const double *aux;       // nonlinear residual: f (residual) or lambda (adjoint)
     double *out;             // Mat values / Dat
     int inc;                 // 1: INC, 0: WRITE
     int num_cus;             // compute units of the device (persistent grids)
@@ -94,6 +95,10 @@ struct AsmArgs {
 hipError_t launch_mat(const AsmArgs &a, hipStream_t s);
 hipError_t launch_vec(const AsmArgs &a, hipStream_t s);
 hipError_t launch_action(const AsmArgs &a, hipStream_t s);
+// Nonlinear residual (mode 0: F from u = x, kappa = coeff, f = aux) and its
+// vector-Jacobian products (1: lambda^T dF/du, 2: lambda^T dF/dkappa, with
+// lambda = aux); P1 Dat plans; fp32 selects binary32 arithmetic.
+hipError_t launch_nl(const AsmArgs &a, int mode, bool fp32, hipStream_t s);
 
 // Per-(dim, degree) launch limits used by the plan builder.
 struct Limits {

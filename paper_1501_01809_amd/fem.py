@@ -21,9 +21,10 @@ STATUS_NAMES = {0: "FEM_OK", 1: "FEM_E_ARG", 2: "FEM_E_RANGE", 3: "FEM_E_OVERFLO
 FEM_READ, FEM_WRITE, FEM_INC = 0, 1, 2
 FEM_TRIANGLE, FEM_TETRAHEDRON = 2, 3
 FEM_FP64, FEM_FP32, FEM_BF16, FEM_FP16 = 0, 1, 2, 3
-FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE = 0, 1, 2, 3
+FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE, FEM_NL_RESIDUAL = 0, 1, 2, 3, 4
 
-KINDS = {"mass": FEM_MASS, "laplace": FEM_LAPLACE, "helmholtz": FEM_HELMHOLTZ, "source": FEM_SOURCE}
+KINDS = {"mass": FEM_MASS, "laplace": FEM_LAPLACE, "helmholtz": FEM_HELMHOLTZ, "source": FEM_SOURCE,
+         "nl_residual": FEM_NL_RESIDUAL}
 
 
 class FemError(RuntimeError):
@@ -68,7 +69,7 @@ class fem_args(C.Structure):
 EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_error", "fem_sync",
            "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
-           "fem_renumber"]
+           "fem_par_loop_assemble_adjoint", "fem_renumber"]
 
 _lib = None
 
@@ -97,6 +98,9 @@ def lib():
                                                 C.POINTER(fem_dat), C.c_int]
         L.fem_apply_action.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_dat),
                                        C.POINTER(fem_dat), C.c_int]
+        L.fem_par_loop_assemble_adjoint.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args),
+                                                    C.POINTER(fem_dat), C.POINTER(fem_dat), C.POINTER(fem_dat),
+                                                    C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
         for name in EXPORTS:
             if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error"):
@@ -149,19 +153,24 @@ def form(kind="helmholtz", cell=3, degree=1, dim=1, prec=FEM_FP64):
 class Args:
     """par_loop arguments over torch device tensors (references kept alive)."""
 
-    def __init__(self, cell_vertex, coords, cell_node, nnodes, coeffs=()):
+    def __init__(self, cell_vertex, coords, cell_node, nnodes, coeffs=(), nodal=False):
+        """coeffs: float64 tensors, on the vertex Set (P1 fields read through
+        cell_vertex) or, with nodal=True, on the node Set (the nonlinear
+        residual's u, kappa, f)."""
         import torch
         assert cell_vertex.dtype == torch.int32 and cell_node.dtype == torch.int32
         assert coords.dtype == torch.float64
         self.cell_vertex, self.coords, self.cell_node = cell_vertex, coords, cell_node
         self.coeffs = list(coeffs)
+        self.nodal = nodal
         self.cells = fem_set(cell_vertex.shape[0])
         self.verts = fem_set(coords.shape[0])
         self.nodes = fem_set(nnodes)
         self.cv = fem_map(C.pointer(self.cells), C.pointer(self.verts), cell_vertex.shape[1], _ptr(cell_vertex))
         self.cn = fem_map(C.pointer(self.cells), C.pointer(self.nodes), cell_node.shape[1], _ptr(cell_node))
         self.X = fem_dat(C.pointer(self.verts), coords.shape[1], _ptr(coords))
-        self.cdats = [fem_dat(C.pointer(self.verts), 1, _ptr(c)) for c in self.coeffs]
+        cset = self.nodes if nodal else self.verts
+        self.cdats = [fem_dat(C.pointer(cset), 1, _ptr(c)) for c in self.coeffs]
         self.c = fem_args()
         self.c.cells = C.pointer(self.cells)
         self.c.cell_vertex = C.pointer(self.cv)
@@ -171,8 +180,8 @@ class Args:
             self.c.coeff[i] = C.pointer(d)
         self.c.ncoeff = len(self.cdats)
 
-    def with_coeffs(self, *coeffs):
-        return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs)
+    def with_coeffs(self, *coeffs, nodal=False):
+        return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs, nodal)
 
 
 class Sparsity:
@@ -239,6 +248,16 @@ def fem_apply_action(ctx: Context, plan: Plan, frm: fem_form, args: Args, x, y, 
     dy = fem_dat(C.pointer(args.nodes), 1, _ptr(y))
     ctx.check(lib().fem_apply_action(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(dx),
                                      C.byref(dy), acc))
+
+
+def fem_par_loop_assemble_adjoint(ctx: Context, plan: Plan, frm: fem_form, args: Args, lam, g_u=None,
+                                  g_kappa=None, acc: int = FEM_WRITE):
+    dl = fem_dat(C.pointer(args.nodes), 1, _ptr(lam))
+    du = fem_dat(C.pointer(args.nodes), 1, _ptr(g_u)) if g_u is not None else None
+    dk = fem_dat(C.pointer(args.nodes), 1, _ptr(g_kappa)) if g_kappa is not None else None
+    ctx.check(lib().fem_par_loop_assemble_adjoint(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(dl),
+                                                  C.byref(du) if du is not None else None,
+                                                  C.byref(dk) if dk is not None else None, acc))
 
 
 def fem_renumber(ctx: Context, frm: fem_form, args: Args):

@@ -1,0 +1,190 @@
+"""GPU parity of the nonlinear residual and its adjoint (vector-Jacobian)
+assembly, in FP64 (bar: 1e-12 of the term-level magnitude per entry) and FP32
+(error against the FP64 oracle reported and bounded), the torch.autograd
+binding against the oracle gradient and central finite differences, and the
+full size of the differentiation workload (512 x 512 x 2 triangles)."""
+import numpy as np
+import pytest
+
+import fem_inputs as fi
+import oracle
+from fem_case import check_close, make_case
+
+pytestmark = pytest.mark.gpu
+
+# FP32 arithmetic (edge vectors formed in FP64, everything after in FP32):
+# measured relative Frobenius errors 7e-8 .. 1.1e-7 and worst per-entry errors
+# (against the term-level magnitude) up to 7.6e-7 at 512 x 512 x 2 triangles.
+# The bars keep about ten times that as margin.
+FP32_REL_FROB = 1e-6
+FP32_REL_ENTRY = 1e-5
+
+
+def _fields(N, seed):
+    st = fi.spawn_streams(seed)
+    return (fi.field(st["u"], N, -1.0, 1.0), fi.field(st["kappa"], N, 0.5, 1.5),
+            fi.field(st["f"], N, -1.0, 1.0), fi.field(st["lam_adj"], N, -1.0, 1.0))
+
+
+class NlRun:
+    def __init__(self, case, prec="fp64"):
+        import torch
+        from paper_1501_01809_amd import fem as F
+        self.F, self.torch = F, torch
+        dev = "cuda"
+        self.case = case
+        self.cv = torch.from_numpy(case.cells).to(dev)
+        self.X = torch.from_numpy(case.coords).to(dev)
+        self.cn = torch.from_numpy(case.cell_node).to(dev)
+        self.ctx = F.Context(0)
+        self.form = F.form("nl_residual", case.dim, 1, prec=F.FEM_FP32 if prec == "fp32" else F.FEM_FP64)
+        self.plan = F.fem_plan_create(self.ctx, self.form, F.Args(self.cv, self.X, self.cn, case.nnodes), None)
+
+    def t(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+    def residual(self, u, k, f):
+        F = self.F
+        out = self.torch.empty(self.case.nnodes, dtype=self.torch.float64, device="cuda")
+        tu, tk, tf = self.t(u), self.t(k), self.t(f)
+        args = F.Args(self.cv, self.X, self.cn, self.case.nnodes, [tu, tk, tf], nodal=True)
+        F.fem_par_loop_assemble_vec(self.ctx, self.plan, self.form, args, out)
+        F.fem_sync(self.ctx)
+        return out.cpu().numpy()
+
+    def adjoint(self, u, k, lam):
+        F = self.F
+        gu = self.torch.empty(self.case.nnodes, dtype=self.torch.float64, device="cuda")
+        gk = self.torch.empty_like(gu)
+        tu, tk, tl = self.t(u), self.t(k), self.t(lam)
+        args = F.Args(self.cv, self.X, self.cn, self.case.nnodes, [tu, tk], nodal=True)
+        F.fem_par_loop_assemble_adjoint(self.ctx, self.plan, self.form, args, tl, gu, gk)
+        F.fem_sync(self.ctx)
+        return gu.cpu().numpy(), gk.cpu().numpy()
+
+
+def _oracle(case, u, k, f, lam):
+    F, Fa = oracle.nl_residual(case.dim, case.cells, case.coords, case.cell_node, u, k, f, case.nnodes)
+    gu, gua, gk, gka = oracle.nl_adjoint(case.dim, case.cells, case.coords, case.cell_node, u, k, lam,
+                                         case.nnodes)
+    return F, Fa, gu, gua, gk, gka
+
+
+@pytest.mark.parametrize("kind,n", [("square", 17), ("cube", 4)])
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_fp64_matches_oracle(kind, n, shuffle):
+    case = make_case(kind, n, 1, seed=4040, shuffle=shuffle)
+    u, k, f, lam = _fields(case.nnodes, 4040)
+    run = NlRun(case)
+    F, Fa, gu, gua, gk, gka = _oracle(case, u, k, f, lam)
+    check_close(run.residual(u, k, f), F, Fa, "residual")
+    g_u, g_k = run.adjoint(u, k, lam)
+    check_close(g_u, gu, gua, "lambda^T dF/du")
+    check_close(g_k, gk, gka, "lambda^T dF/dkappa")
+    # bitwise reproducible
+    assert np.array_equal(run.residual(u, k, f).view(np.uint64), run.residual(u, k, f).view(np.uint64))
+
+
+def _fp32_errors(got, ref, absref):
+    frob = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    entry = float(np.max(np.abs(got - ref) / np.maximum(absref, 1e-300)))
+    return frob, entry
+
+
+@pytest.mark.parametrize("kind,n", [("square", 17), ("cube", 4)])
+def test_fp32_error_against_fp64_oracle(kind, n):
+    case = make_case(kind, n, 1, seed=4041, shuffle=True)
+    u, k, f, lam = _fields(case.nnodes, 4041)
+    run = NlRun(case, "fp32")
+    F, Fa, gu, gua, gk, gka = _oracle(case, u, k, f, lam)
+    g_u, g_k = run.adjoint(u, k, lam)
+    for name, got, ref, ab in (("residual", run.residual(u, k, f), F, Fa), ("g_u", g_u, gu, gua),
+                               ("g_kappa", g_k, gk, gka)):
+        frob, entry = _fp32_errors(got, ref, ab)
+        print(f"FP32 {kind} {name}: relative Frobenius {frob:.2e}, worst entry/magnitude {entry:.2e}")
+        assert frob <= FP32_REL_FROB and entry <= FP32_REL_ENTRY, (name, frob, entry)
+
+
+def test_autograd_matches_oracle_and_finite_differences():
+    import torch
+    from paper_1501_01809_amd import fem as F
+    from paper_1501_01809_amd.autograd import NonlinearResidual, ResidualOp
+    case = make_case("square", 12, 1, seed=4042, shuffle=True)
+    u, k, f, lam = _fields(case.nnodes, 4042)
+    dev = "cuda"
+    ctx = F.Context(0)
+    op = ResidualOp(ctx, torch.from_numpy(case.cells).to(dev), torch.from_numpy(case.coords).to(dev),
+                    torch.from_numpy(case.cell_node).to(dev), case.nnodes)
+    tu = torch.from_numpy(u).to(dev).requires_grad_(True)
+    tk = torch.from_numpy(k).to(dev).requires_grad_(True)
+    tf = torch.from_numpy(f).to(dev)
+    tl = torch.from_numpy(lam).to(dev)
+    res = NonlinearResidual.apply(tu, tk, tf, op)
+    (res * tl).sum().backward()
+    F.fem_sync(ctx)
+    _, _, gu, gua, gk, gka = _oracle(case, u, k, f, lam)
+    check_close(tu.grad.cpu().numpy(), gu, gua, "autograd u")
+    check_close(tk.grad.cpu().numpy(), gk, gka, "autograd kappa")
+    # central differences (h = 1e-6) of lambda . F(u, kappa), F from the GPU forward
+    rng = np.random.default_rng(9)
+    du = rng.uniform(-1, 1, case.nnodes); dk = rng.uniform(-1, 1, case.nnodes)
+    run = NlRun(case)
+    h = 1e-6
+    L = lambda uu, kk: lam @ run.residual(uu, kk, f)
+    fd_u = (L(u + h * du, k) - L(u - h * du, k)) / (2 * h)
+    fd_k = (L(u, k + h * dk) - L(u, k - h * dk)) / (2 * h)
+    assert abs(fd_u - tu.grad.cpu().numpy() @ du) <= 1e-7 * max(1.0, abs(fd_u))
+    assert abs(fd_k - tk.grad.cpu().numpy() @ dk) <= 1e-7 * max(1.0, abs(fd_k))
+
+
+def test_differentiation_workload_full_size():
+    """512 x 512 x 2 triangles (524,288 cells), jittered, shuffled: every entry
+    of the FP64 residual and adjoint against the oracle; FP32 errors bounded."""
+    case = make_case("square", 512, 1, seed=1501, shuffle=True)
+    assert case.cells.shape[0] == 524288
+    u, k, f, lam = _fields(case.nnodes, 1501)
+    F, Fa, gu, gua, gk, gka = _oracle(case, u, k, f, lam)
+    run = NlRun(case)
+    check_close(run.residual(u, k, f), F, Fa, "residual 512^2")
+    g_u, g_k = run.adjoint(u, k, lam)
+    check_close(g_u, gu, gua, "g_u 512^2")
+    check_close(g_k, gk, gka, "g_kappa 512^2")
+    r32 = NlRun(case, "fp32")
+    g_u32, g_k32 = r32.adjoint(u, k, lam)
+    for name, got, ref, ab in (("residual", r32.residual(u, k, f), F, Fa), ("g_u", g_u32, gu, gua),
+                               ("g_kappa", g_k32, gk, gka)):
+        frob, entry = _fp32_errors(got, ref, ab)
+        print(f"FP32 512^2 {name}: relative Frobenius {frob:.2e}, worst entry/magnitude {entry:.2e}")
+        assert frob <= FP32_REL_FROB and entry <= FP32_REL_ENTRY, (name, frob, entry)
+
+
+def test_rejections():
+    import torch
+    from paper_1501_01809_amd import fem as F
+    case = make_case("square", 4, 1, seed=1)
+    dev = "cuda"
+    cv = torch.from_numpy(case.cells).to(dev); X = torch.from_numpy(case.coords).to(dev)
+    cn = torch.from_numpy(case.cell_node).to(dev)
+    ctx = F.Context(0)
+    args = F.Args(cv, X, cn, case.nnodes)
+    with pytest.raises(F.FemError) as e:
+        F.fem_plan_create(ctx, F.form("nl_residual", 2, 2), args, None)
+    assert e.value.status == F.FEM_E_UNSUPPORTED
+    c2 = make_case("square", 4, 2, seed=1)
+    with pytest.raises(F.FemError):
+        F.fem_plan_create(ctx, F.form("nl_residual", 2, 1, prec=F.FEM_BF16), args, None)
+    plan = F.fem_plan_create(ctx, F.form("nl_residual", 2, 1), args, None)
+    lam = torch.zeros(case.nnodes, dtype=torch.float64, device=dev)
+    g = torch.zeros_like(lam)
+    with pytest.raises(F.FemError) as e:      # coefficients must be nodal Dats, three for the residual
+        F.fem_par_loop_assemble_vec(ctx, plan, F.form("nl_residual", 2, 1), args.with_coeffs(lam, nodal=True), g)
+    assert e.value.status == F.FEM_E_ARG
+    with pytest.raises(F.FemError) as e:      # the adjoint needs the residual's kind
+        F.fem_par_loop_assemble_adjoint(ctx, plan, F.form("helmholtz", 2, 1),
+                                        args.with_coeffs(lam, lam, nodal=True), lam, g, None)
+    assert e.value.status == F.FEM_E_ARG
+    with pytest.raises(F.FemError) as e:      # an output may not alias lambda
+        F.fem_par_loop_assemble_adjoint(ctx, plan, F.form("nl_residual", 2, 1),
+                                        args.with_coeffs(g, g, nodal=True), lam, lam, None)
+    assert e.value.status == F.FEM_E_ARG
+    del c2
