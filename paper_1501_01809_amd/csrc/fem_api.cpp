@@ -599,6 +599,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     p->nblk = b;
     p->lbits = lbits;
     p->cell_visits = (int64_t)bcell.size();
+    for (int32_t i = 0; i < b; ++i) p->max_blk_cells = std::max(p->max_blk_cells, blk_cptr[i + 1] - blk_cptr[i]);
     p->cell_node = args->cell_node->values;
     p->row_ptr = is_mat ? sp->row_ptr : nullptr;
     std::vector<int32_t> bverts(bcell.size() * (dim + 1));
@@ -819,16 +820,13 @@ fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, con
     a.aux = lambda->data;
     a.inc = acc == FEM_INC;
     const bool fp32 = form->prec == FEM_FP32;
-    if (g_u) {
-        a.out = g_u->data;
-        hipError_t e = femk::launch_nl(a, 1, fp32, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
-    }
-    if (g_kappa) {
-        a.out = g_kappa->data;
-        hipError_t e = femk::launch_nl(a, 2, fp32, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
-    }
+    // both products from one gather when both are asked for
+    const int mode = g_u && g_kappa ? 3 : g_u ? 1 : 2;
+    if (!g_u && !g_kappa) return FEM_OK;
+    a.out = g_u ? g_u->data : g_kappa->data;
+    a.out2 = g_u && g_kappa ? g_kappa->data : nullptr;
+    hipError_t e = femk::launch_nl(a, mode, fp32, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
     return FEM_OK;
 }
 

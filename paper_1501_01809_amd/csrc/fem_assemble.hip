@@ -46,7 +46,6 @@ struct KArgs {
     const int32_t *__restrict__ cell_node;
     const double *__restrict__ coeff;
     const double *__restrict__ x;
-    const double *__restrict__ aux;
     double *__restrict__ out;
     double cstiff, cmass;
     int inc;
@@ -60,7 +59,7 @@ KArgs kargs(const AsmArgs &a)
     k.inc_ptr = p.inc_ptr; k.ent = p.ent;
     k.blk_hdr = p.blk_hdr; k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint32_t *>(p.pstream);
     k.row_ptr = a.row_ptr; k.coords = a.coords;
-    k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.aux = a.aux; k.out = a.out;
+    k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
     return k;
 }
@@ -695,166 +694,6 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
     }
 
 namespace {
-// ---------------------------------------------------------------- nonlinear residual
-
-// Exact integral over a simplex of dimension D of the product of the
-// barycentrics l_m l_n l_p l_i (W4) or l_m l_i (W2), divided by the volume:
-// D! prod(a!) / (|a| + D)! for the exponent multi-index a.
-constexpr double nl_fact(int n) { return n <= 1 ? 1.0 : n * nl_fact(n - 1); }
-template <int D>
-constexpr double nl_moment(int m, int n, int p, int i, int deg)
-{
-    double num = 1.0;
-    for (int v = 0; v <= D; ++v) {
-        const int c = (m == v) + (n == v) + (deg == 4 ? (p == v) + (i == v) : 0);
-        num *= nl_fact(c);
-    }
-    return nl_fact(D) * num / nl_fact(deg + D);
-}
-
-// Local values of one P1 cell of the residual kappa grad(u).grad(v) +
-// u^3 v - f v (MODE 0) or of its vector-Jacobian products with lambda (MODE
-// 1: d/du, MODE 2: d/dkappa); w holds f (MODE 0) or lambda.  Every integral
-// is exact: integral of kappa = |K| mean(kappa), |K| grad(l_m).grad(l_n) =
-// (a_m . a_n) / (|det J| D!) with a_m the rows of adj(J), and the barycentric
-// moments above.  c holds the edge vectors x_{q+1} - x_0, formed in FP64 by
-// the caller so that a narrower R does not lose the short edges of a fine
-// mesh to cancellation; all other arithmetic in R.
-template <int D, int MODE, typename R>
-__device__ __forceinline__ void nl_local(const R (&c)[D][D], const R (&u)[D + 1], const R (&k)[D + 1],
-                                         const R (&w)[D + 1], R (&loc)[D + 1])
-{
-    constexpr int NV = D + 1;
-    R a[NV][D], det;
-    if constexpr (D == 2) {
-        const R c1x = c[0][0], c1y = c[0][1], c2x = c[1][0], c2y = c[1][1];
-        det = c1x * c2y - c1y * c2x;
-        a[1][0] = c2y; a[1][1] = -c2x; a[2][0] = -c1y; a[2][1] = c1x;
-    } else {
-        a[1][0] = c[1][1] * c[2][2] - c[1][2] * c[2][1];
-        a[1][1] = c[1][2] * c[2][0] - c[1][0] * c[2][2];
-        a[1][2] = c[1][0] * c[2][1] - c[1][1] * c[2][0];
-        a[2][0] = c[2][1] * c[0][2] - c[2][2] * c[0][1];
-        a[2][1] = c[2][2] * c[0][0] - c[2][0] * c[0][2];
-        a[2][2] = c[2][0] * c[0][1] - c[2][1] * c[0][0];
-        a[3][0] = c[0][1] * c[1][2] - c[0][2] * c[1][1];
-        a[3][1] = c[0][2] * c[1][0] - c[0][0] * c[1][2];
-        a[3][2] = c[0][0] * c[1][1] - c[0][1] * c[1][0];
-        det = c[0][0] * a[1][0] + c[0][1] * a[1][1] + c[0][2] * a[1][2];
-    }
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-        R s = 0;
-#pragma unroll
-        for (int m = 1; m < NV; ++m) s += a[m][r];
-        a[0][r] = -s;
-    }
-    const R adet = det < R(0) ? -det : det;
-    const R vol = adet / R(nl_fact(D));
-    const R sc = R(1) / (adet * R(nl_fact(D)));   // |K| grad l_m . grad l_n = (a_m . a_n) * sc
-    R kbar = 0;
-#pragma unroll
-    for (int m = 0; m < NV; ++m) kbar += k[m];
-    kbar = kbar / R(NV);
-    // grad(u) and grad(w) scaled: (sum_m u_m a_m)
-    R gu[D], gw[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-        gu[r] = 0; gw[r] = 0;
-#pragma unroll
-        for (int m = 0; m < NV; ++m) { gu[r] += u[m] * a[m][r]; gw[r] += w[m] * a[m][r]; }
-    }
-    if constexpr (MODE == 2) {
-        R t = 0;
-#pragma unroll
-        for (int r = 0; r < D; ++r) t += gu[r] * gw[r];
-        t = t * sc / R(NV);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) loc[i] = t;
-    } else {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            R g = 0;
-#pragma unroll
-            for (int r = 0; r < D; ++r) g += (MODE == 0 ? gu[r] : gw[r]) * a[i][r];
-            R cub = 0;
-#pragma unroll
-            for (int m = 0; m < NV; ++m)
-#pragma unroll
-                for (int n = 0; n < NV; ++n) {
-                    const R umn = u[m] * u[n];
-#pragma unroll
-                    for (int p = 0; p < NV; ++p)
-                        cub += umn * (MODE == 0 ? u[p] : w[p]) * R(nl_moment<D>(m, n, p, i, 4));
-                }
-            if constexpr (MODE == 0) {
-                R src = 0;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) src += w[m] * R(nl_moment<D>(m, i, 0, 0, 2));
-                loc[i] = kbar * g * sc + vol * (cub - src);
-            } else {
-                loc[i] = kbar * g * sc + R(3) * vol * cub;
-            }
-        }
-    }
-}
-
-// Row-owned Dat assembly of the nonlinear residual or of one of its
-// vector-Jacobian products, on a P1 Dat plan: the same schedule as the
-// source vector (each lane computes one cell's local values into LDS, each
-// row sums its cells' values in ascending cell order), arithmetic in R.
-template <int D, int MODE, typename R>
-__global__ __launch_bounds__(VWG) void k_assemble_nl(KArgs a)
-{
-    constexpr int NL = D + 1, LB = lbits_for(NL);
-    constexpr int CAP = VLDS / NL;
-    __shared__ R vk[CAP * NL];
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
-    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
-    for (int c = tid; c < nc; c += VWG) {
-        const int64_t cell = a.bcell[c0 + c];
-        double x[NL][D];
-        R e[D][D], u[NL], k[NL], w[NL], loc[NL];
-#pragma unroll
-        for (int m = 0; m < NL; ++m) {
-            const int64_t v = a.bverts[(int64_t)(c0 + c) * NL + m];
-#pragma unroll
-            for (int r = 0; r < D; ++r) x[m][r] = a.coords[v * D + r];
-            const int64_t nd = a.cell_node[cell * NL + m];
-            u[m] = R(a.x[nd]);
-            k[m] = R(a.coeff[nd]);
-            w[m] = R(a.aux[nd]);
-        }
-#pragma unroll
-        for (int q = 0; q < D; ++q)
-#pragma unroll
-            for (int r = 0; r < D; ++r) e[q][r] = R(x[q + 1][r] - x[0][r]);
-        nl_local<D, MODE, R>(e, u, k, w, loc);
-#pragma unroll
-        for (int j = 0; j < NL; ++j) vk[c * NL + j] = loc[j];
-    }
-    lds_barrier();
-    for (int r = r0 + tid; r < r1; r += VWG) {
-        R acc = 0;
-        for (int e = a.inc_ptr[r]; e < a.inc_ptr[r + 1]; ++e) {
-            const uint32_t pe = a.ent[e];
-            acc += vk[(int)(pe >> LB) * NL + (int)(pe & ((1u << LB) - 1))];
-        }
-        a.out[r] = a.inc ? a.out[r] + (double)acc : (double)acc;
-    }
-}
-
-template <int D, int MODE>
-hipError_t nl_launch(const AsmArgs &a, bool fp32, hipStream_t s)
-{
-    if (fp32)
-        hipLaunchKernelGGL((k_assemble_nl<D, MODE, float>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
-    else
-        hipLaunchKernelGGL((k_assemble_nl<D, MODE, double>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
-    return hipGetLastError();
-}
-
 template <int D, int K>
 hipError_t vec_dispatch(const AsmArgs &a, hipStream_t s)
 {
@@ -879,22 +718,6 @@ hipError_t launch_vec(const AsmArgs &a, hipStream_t s)
 {
     if (a.plan->nblk == 0) return hipSuccess;
     FEM_DISPATCH(vec_dispatch, a, s)
-}
-
-hipError_t launch_nl(const AsmArgs &a, int mode, bool fp32, hipStream_t s)
-{
-    if (a.plan->nblk == 0) return hipSuccess;
-    if (a.plan->degree != 1) return hipErrorInvalidValue;
-    const int key = a.plan->dim * 10 + mode;
-    switch (key) {
-    case 20: return nl_launch<2, 0>(a, fp32, s);
-    case 21: return nl_launch<2, 1>(a, fp32, s);
-    case 22: return nl_launch<2, 2>(a, fp32, s);
-    case 30: return nl_launch<3, 0>(a, fp32, s);
-    case 31: return nl_launch<3, 1>(a, fp32, s);
-    case 32: return nl_launch<3, 2>(a, fp32, s);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_action(const AsmArgs &a, hipStream_t s)

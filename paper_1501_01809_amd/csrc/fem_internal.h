@@ -45,6 +45,7 @@ struct fem_plan {
     int64_t nchunks = 0;         // Mat plans: chunks over all blocks
     int64_t stream_entries = 0;  // Mat plans: 16-bit stream entries (padding included)
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
+    int32_t max_blk_cells = 0;   // most cells any block gathers
     size_t bytes = 0;            // device bytes held
     // device arrays (owned)
     int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
@@ -89,6 +90,7 @@ struct AsmArgs {
     const double *x;         // action input; u of the nonlinear residual
     const double *aux;       // nonlinear residual: f (residual) or lambda (adjoint)
     double *out;             // Mat values / Dat
+    double *out2;            // nonlinear residual, mode 3: lambda^T dF/dkappa
     int inc;                 // 1: INC, 0: WRITE
     int num_cus;             // compute units of the device (persistent grids)
 };
@@ -97,7 +99,8 @@ hipError_t launch_vec(const AsmArgs &a, hipStream_t s);
 hipError_t launch_action(const AsmArgs &a, hipStream_t s);
 // Nonlinear residual (mode 0: F from u = x, kappa = coeff, f = aux) and its
 // vector-Jacobian products (1: lambda^T dF/du, 2: lambda^T dF/dkappa, with
-// lambda = aux); P1 Dat plans; fp32 selects binary32 arithmetic.
+// lambda = aux; 3: both, into out and out2); P1 Dat plans; fp32 selects
+// binary32 arithmetic.
 hipError_t launch_nl(const AsmArgs &a, int mode, bool fp32, hipStream_t s);
 
 // Per-(dim, degree) launch limits used by the plan builder.

@@ -52,15 +52,17 @@ class NlRun:
         F.fem_sync(self.ctx)
         return out.cpu().numpy()
 
-    def adjoint(self, u, k, lam):
+    def adjoint(self, u, k, lam, want_u=True, want_k=True):
+        """Both products from one call (one fused launch), or one of them."""
         F = self.F
         gu = self.torch.empty(self.case.nnodes, dtype=self.torch.float64, device="cuda")
         gk = self.torch.empty_like(gu)
         tu, tk, tl = self.t(u), self.t(k), self.t(lam)
         args = F.Args(self.cv, self.X, self.cn, self.case.nnodes, [tu, tk], nodal=True)
-        F.fem_par_loop_assemble_adjoint(self.ctx, self.plan, self.form, args, tl, gu, gk)
+        F.fem_par_loop_assemble_adjoint(self.ctx, self.plan, self.form, args, tl, gu if want_u else None,
+                                        gk if want_k else None)
         F.fem_sync(self.ctx)
-        return gu.cpu().numpy(), gk.cpu().numpy()
+        return (gu.cpu().numpy() if want_u else None), (gk.cpu().numpy() if want_k else None)
 
 
 def _oracle(case, u, k, f, lam):
@@ -81,8 +83,30 @@ def test_fp64_matches_oracle(kind, n, shuffle):
     g_u, g_k = run.adjoint(u, k, lam)
     check_close(g_u, gu, gua, "lambda^T dF/du")
     check_close(g_k, gk, gka, "lambda^T dF/dkappa")
+    # one product at a time (separate kernels from the fused pair)
+    check_close(run.adjoint(u, k, lam, want_k=False)[0], gu, gua, "lambda^T dF/du alone")
+    check_close(run.adjoint(u, k, lam, want_u=False)[1], gk, gka, "lambda^T dF/dkappa alone")
     # bitwise reproducible
     assert np.array_equal(run.residual(u, k, f).view(np.uint64), run.residual(u, k, f).view(np.uint64))
+
+
+def test_inc_adds_to_outputs():
+    import torch
+    from paper_1501_01809_amd import fem as F
+    case = make_case("square", 9, 1, seed=4043, shuffle=True)
+    u, k, f, lam = _fields(case.nnodes, 4043)
+    run = NlRun(case)
+    F_, Fa, gu, gua, gk, gka = _oracle(case, u, k, f, lam)
+    base = np.linspace(-1.0, 1.0, case.nnodes)
+    outs = [run.t(base.copy()) for _ in range(3)]
+    args3 = F.Args(run.cv, run.X, run.cn, case.nnodes, [run.t(u), run.t(k), run.t(f)], nodal=True)
+    F.fem_par_loop_assemble_vec(run.ctx, run.plan, run.form, args3, outs[0], F.FEM_INC)
+    args2 = F.Args(run.cv, run.X, run.cn, case.nnodes, [run.t(u), run.t(k)], nodal=True)
+    F.fem_par_loop_assemble_adjoint(run.ctx, run.plan, run.form, args2, run.t(lam), outs[1], outs[2], F.FEM_INC)
+    F.fem_sync(run.ctx)
+    for o, ref, ab, name in zip(outs, (F_, gu, gk), (Fa, gua, gka), ("F", "g_u", "g_kappa")):
+        check_close(o.cpu().numpy() - base, ref, ab + np.abs(base), name + " INC")
+    del torch
 
 
 def _fp32_errors(got, ref, absref):
