@@ -134,6 +134,74 @@ def cpu_baseline(d, degree, sample_cells):
                       f"{len(os.sched_getaffinity(0))} host cores visible"}
 
 
+def bench_nl(ctx, steps: int, warmup: int, seed: int, n: int = 512):
+    """The differentiation workload: the P1 residual
+    F(u, kappa)_i = integral of kappa grad(u).grad(v_i) + u^3 v_i - f v_i and its
+    vector-Jacobian products lambda^T dF/du, lambda^T dF/dkappa on the unit
+    square, n x n x 2 triangles jittered by U[-0.2h, 0.2h], shuffled then
+    Hilbert-renumbered; u U[-1,1], kappa U[0.5,1.5], f U[-1,1], lambda U[-1,1]
+    on the nodes.  Timed per call with HIP events, FP64 and FP32 arithmetic."""
+    import torch
+    import fem_inputs as fi
+    from paper_1501_01809_amd import fem as F
+    dev = torch.device("cuda:0")
+    st = fi.spawn_streams(seed)
+    m = fi.jitter_interior(fi.unit_square(n), 0.2, st["mesh"])
+    cn, N = fi.node_map(m, 1)
+    rng = np.random.default_rng(seed + 1)
+    cells, cn = fi.permute_cells(rng.permutation(m.ncells), m.cells, cn)
+    vp = rng.permutation(m.nverts)
+    vinv = np.empty_like(vp); vinv[vp] = np.arange(vp.size)
+    cells = np.ascontiguousarray(vinv[cells].astype(np.int32))
+    coords = np.ascontiguousarray(m.coords[vp])
+    cn = np.ascontiguousarray(cn, dtype=np.int32)
+    C, V = cells.shape[0], coords.shape[0]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g_cv, g_X, g_cn = t(cells), t(coords), t(cn)
+    f64 = F.form("nl_residual", 2, 1)
+    cp, vperm, nperm = F.fem_renumber(ctx, f64, F.Args(g_cv, g_X, g_cn, N))
+    vi = np.empty_like(vperm); vi[vperm] = np.arange(vperm.size)
+    ni = np.empty_like(nperm); ni[nperm] = np.arange(nperm.size)
+    cells = np.ascontiguousarray(vi[cells[cp]].astype(np.int32))
+    cn = np.ascontiguousarray(ni[cn[cp]].astype(np.int32))
+    coords = np.ascontiguousarray(coords[vperm])
+    g_cv, g_X, g_cn = t(cells), t(coords), t(cn)
+    u, kap, f, lam = (t(fi.field(st[k], N, lo, hi)) for k, lo, hi in
+                      (("u", -1.0, 1.0), ("kappa", 0.5, 1.5), ("f", -1.0, 1.0), ("lam_adj", -1.0, 1.0)))
+    res = torch.empty(N, dtype=torch.float64, device=dev)
+    gu, gk = torch.empty_like(res), torch.empty_like(res)
+    a3 = F.Args(g_cv, g_X, g_cn, N, [u, kap, f], nodal=True)
+    a2 = F.Args(g_cv, g_X, g_cn, N, [u, kap], nodal=True)
+    stream = torch.cuda.current_stream(dev)
+    per_launch = 4 * C * 3 * 2 + 8 * V * 2 + 8 * N * 3 + 8 * N   # maps, coords, 3 node fields, 1 output
+    out = {"workload": f"P1 nonlinear residual and adjoint on the unit square, {n}x{n}x2 triangles "
+                       f"({C} cells, {N} nodes), jitter 0.2h", "cells": C, "nodes": N}
+    for name, prec in (("fp64", F.FEM_FP64), ("fp32", F.FEM_FP32)):
+        frm = F.form("nl_residual", 2, 1, prec=prec)
+        plan = F.fem_plan_create(ctx, frm, F.Args(g_cv, g_X, g_cn, N), None)
+        calls = {"residual": (lambda: F.fem_par_loop_assemble_vec(ctx, plan, frm, a3, res), per_launch),
+                 # both products from one launch: one gather, two outputs
+                 "adjoint": (lambda: F.fem_par_loop_assemble_adjoint(ctx, plan, frm, a2, lam, gu, gk),
+                             per_launch + 8 * N)}
+        rec = {}
+        for op, (fn, by) in calls.items():
+            for _ in range(warmup):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for k in range(steps):
+                fn()
+                ev[k + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+            rec[op] = {"ms": float(ms.mean()), "ms_min": float(ms.min()), "cells_per_s": C / (ms.mean() * 1e-3),
+                       "alg_bytes": by, "GBps": by / (ms.mean() * 1e-3) / 1e9,
+                       "hbm_frac": by / (ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[name] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +213,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-renumber", action="store_true")
+    ap.add_argument("--no-nl", action="store_true",
+                    help="skip the differentiation workload (residual and adjoint, 512x512x2 triangles)")
     ap.add_argument("--ops", default="mat,vec,action",
                     help="operations run in a step (a subset is for profiling the kernels one by one; "
                          "the reported metric needs all three)")
@@ -287,6 +357,8 @@ def main():
         "setup_ms": setup,
         "host": platform.node(),
     }
+    if not args.no_nl:
+        out["differentiation"] = bench_nl(ctx, args.steps, args.warmup, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C))
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
