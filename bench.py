@@ -36,10 +36,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_inputs(n: int, degree: int, seed: int):
+def build_inputs(n: int, degree: int, seed: int, mesh: str = "cube"):
     import fem_inputs as fi
     st = fi.spawn_streams(seed)
-    m = fi.jitter_interior(fi.unit_cube(n), 0.2, st["mesh"])
+    m = fi.jitter_interior(fi.unit_cube(n) if mesh == "cube" else fi.unit_square(n), 0.2, st["mesh"])
     cn, N = fi.node_map(m, degree)
     kappa = fi.field(st["kappa"], m.nverts, 0.5, 1.5)
     f = fi.field(st["f"], m.nverts, -1.0, 1.0)
@@ -89,7 +89,7 @@ def measured_traffic(args, name):
     by the factor a plain copy of known size gives), or None when the summary
     is missing, was taken for another workload, or the kernel sources changed
     since (its recorded source hash differs)."""
-    if args.n != 64 or args.degree != 2 or args.no_renumber:
+    if args.n != 64 or args.degree != 2 or args.no_renumber or args.mesh != "cube":
         return None
     path = os.path.join(ROOT, "profiles", name + "_traffic.md")
     if not os.path.exists(path):
@@ -108,7 +108,7 @@ def measured_traffic(args, name):
         return None
 
 
-def cpu_baseline(d, degree, sample_cells):
+def cpu_baseline(d, degree, sample_cells, dim=3):
     """The oracle, as it stands, on the first `sample_cells` cells of the same
     (renumbered) mesh: sparsity + matrix + vector + action, one thread."""
     import oracle
@@ -116,9 +116,9 @@ def cpu_baseline(d, degree, sample_cells):
     oracle.lib()
     t0 = time.perf_counter()
     rp, ci = oracle.sparsity(cn, d["N"])
-    oracle.assemble_mat(3, degree, cells, d["coords"], cn, d["kappa"], rp, ci)
-    oracle.assemble_vec(3, degree, cells, d["coords"], cn, d["f"], d["N"])
-    oracle.apply_action(3, degree, cells, d["coords"], cn, d["kappa"], d["x"], d["N"])
+    oracle.assemble_mat(dim, degree, cells, d["coords"], cn, d["kappa"], rp, ci)
+    oracle.assemble_vec(dim, degree, cells, d["coords"], cn, d["f"], d["N"])
+    oracle.apply_action(dim, degree, cells, d["coords"], cn, d["kappa"], d["x"], d["N"])
     t = time.perf_counter() - t0
     cpu = "unknown"
     try:
@@ -207,7 +207,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=64, help="cubes per side")
+    ap.add_argument("--n", type=int, default=64, help="cubes (or squares) per side")
+    ap.add_argument("--mesh", choices=("cube", "square"), default="cube",
+                    help="n^3 x 6 Kuhn tetrahedra (default) or n x n x 2 triangles")
     ap.add_argument("--degree", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1501)
     ap.add_argument("--cpu-sample", type=int, default=16384)
@@ -240,7 +242,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": 8 * n, "calibrate_copy_bytes_written": 8 * n}))
         return
     t0 = time.perf_counter()
-    d = build_inputs(args.n, args.degree, args.seed)
+    d = build_inputs(args.n, args.degree, args.seed, args.mesh)
+    dim = 3 if args.mesh == "cube" else 2
     log(f"inputs: {d['cells'].shape[0]} cells, {d['N']} nodes ({time.perf_counter() - t0:.1f} s)")
     ctx = F.Context(0)
     C = d["cells"].shape[0]
@@ -250,8 +253,8 @@ def main():
                     cn=torch.from_numpy(dd["cn"]).to(dev), kappa=torch.from_numpy(dd["kappa"]).to(dev),
                     f=torch.from_numpy(dd["f"]).to(dev), x=torch.from_numpy(dd["x"]).to(dev))
 
-    form = F.form("helmholtz", 3, args.degree)
-    src = F.form("source", 3, args.degree)
+    form = F.form("helmholtz", dim, args.degree)
+    src = F.form("source", dim, args.degree)
     setup = {}
     g = upload(d)
     if not args.no_renumber:
@@ -312,8 +315,8 @@ def main():
 
     # algorithmic bytes per launch (one read of inputs and structure, one write of outputs)
     V = d["coords"].shape[0]; nl = d["cn"].shape[1]
-    maps = 4 * C * nl + 4 * C * 4
-    vdata = 8 * V * 3 + 8 * V
+    maps = 4 * C * nl + 4 * C * (dim + 1)
+    vdata = 8 * V * dim + 8 * V
     mat_bytes = maps + vdata + 8 * (N + 1) + 4 * nnz + 8 * nnz
     vec_bytes = maps + vdata + 8 * N
     act_bytes = maps + vdata + 8 * N + 8 * N
@@ -342,15 +345,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"P{args.degree} Lagrange Helmholtz on the unit cube, {args.n}^3x6 "
-                               f"Kuhn tets ({C} cells, {N} DOFs, nnz {nnz}), jitter 0.2h, kappa P1 "
+        "config": {"workload": f"P{args.degree} Lagrange Helmholtz on the unit "
+                               + (f"cube, {args.n}^3x6 Kuhn tets" if dim == 3 else
+                                  f"square, {args.n}x{args.n}x2 triangles")
+                               + f" ({C} cells, {N} DOFs, nnz {nnz}), jitter 0.2h, kappa P1 "
                                f"U[0.5,1.5], f P1 U[-1,1]; step = CSR matrix + source vector + "
                                f"matrix-free action, FP64",
                    "cells": C, "dofs": N, "nnz": nnz, "renumbered": not args.no_renumber},
         "roofline": {"bound": "hbm", "achieved": gbs(mat_bytes, mat_ms), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs(mat_bytes, mat_ms) / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args, "k_assemble_mat_p2tet64"),
-                     "kernel": "k_assemble_mat<3,2>", "alg_bytes_per_launch": mat_bytes},
+                     "kernel": f"k_assemble_mat<{dim},{args.degree}>", "alg_bytes_per_launch": mat_bytes},
         "ops": ops,
         "step_ms_p50": float(np.percentile(per[:, 3], 50)),
         "step_ms_p99": float(np.percentile(per[:, 3], 99)),
@@ -360,7 +365,7 @@ def main():
     if not args.no_nl:
         out["differentiation"] = bench_nl(ctx, args.steps, args.warmup, args.seed)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C))
+        out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C), dim)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 
