@@ -13,10 +13,11 @@ benchmark shapes (unit square and unit cube, experiments section).
 """
 from .meshes import (Mesh, unit_square, unit_cube, two_triangles, two_tets,
                      jitter_interior, node_map, permute_cells, permute_nodes,
-                     permute_vertices, local_node_barycentrics)
+                     permute_vertices, local_node_barycentrics, dg_coordinates,
+                     flatten_cells)
 from .fields import field, seeds, spawn_streams
 
 __all__ = ["Mesh", "unit_square", "unit_cube", "two_triangles", "two_tets",
            "jitter_interior", "node_map", "permute_cells", "permute_nodes",
-           "permute_vertices", "local_node_barycentrics", "field", "seeds",
-           "spawn_streams"]
+           "permute_vertices", "local_node_barycentrics", "dg_coordinates",
+           "flatten_cells", "field", "seeds", "spawn_streams"]

@@ -2,14 +2,14 @@
 
 Each input field draws from its own NumPy PCG64 stream, spawned from a single
 base seed with ``SeedSequence(seed).spawn``, in the fixed stream order
-mesh, kappa, f, x, mu, lam, u, lam_adj; adding a field never shifts the values
-of another.
+mesh, kappa, f, x, mu, lam, u, lam_adj, flatten; adding a field never shifts
+the values of another.
 """
 from __future__ import annotations
 
 import numpy as np
 
-STREAMS = ("mesh", "kappa", "f", "x", "mu", "lam", "u", "lam_adj")
+STREAMS = ("mesh", "kappa", "f", "x", "mu", "lam", "u", "lam_adj", "flatten")
 BASE_SEED = 1501
 
 

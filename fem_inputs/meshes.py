@@ -128,6 +128,38 @@ def jitter_interior(mesh: Mesh, amplitude: float, rng: np.random.Generator) -> M
                 dict(mesh.meta, jitter=amplitude))
 
 
+def dg_coordinates(mesh: Mesh) -> np.ndarray:
+    """Per-cell (discontinuous) copy of the vertex coordinates, float64
+    [C][d+1][d]: coordinates as an ordinary field on its own cell-to-node Map
+    (the mesh abstraction treats them so), which lets single cells be
+    reshaped without moving their neighbours."""
+    return np.ascontiguousarray(mesh.coords[mesh.cells])
+
+
+def flatten_cells(xdg: np.ndarray, fraction: float, rng: np.random.Generator, ratio: float = 1e3):
+    """Flatten round(fraction * C) tetrahedra of a per-cell coordinate field.
+
+    The cells are the first ones of a seeded permutation (returned sorted).  In
+    each, vertex 3 moves along the normal of the face (v0, v1, v2), staying on
+    its side, to the height (longest edge of that face) / ratio above the
+    face's plane; the aspect ratio becomes about ``ratio`` and the orientation
+    is kept.  Returns (new coordinates, chosen cell ids).
+    """
+    C = xdg.shape[0]
+    k = int(round(fraction * C))
+    chosen = np.sort(rng.permutation(C)[:k])
+    x = xdg.copy()
+    v0, v1, v2, v3 = (x[chosen, m] for m in range(4))
+    nrm = np.cross(v1 - v0, v2 - v0)
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    h = np.einsum("ij,ij->i", v3 - v0, nrm)
+    L = np.maximum(np.maximum(np.linalg.norm(v1 - v0, axis=1), np.linalg.norm(v2 - v0, axis=1)),
+                   np.linalg.norm(v2 - v1, axis=1))
+    foot = v3 - h[:, None] * nrm
+    x[chosen, 3] = foot + (np.sign(h) * L / ratio)[:, None] * nrm
+    return np.ascontiguousarray(x), chosen
+
+
 def local_node_barycentrics(dim: int, degree: int) -> np.ndarray:
     """Integer barycentric weights (rows sum to ``degree``) of the local nodes."""
     nv = dim + 1

@@ -4,7 +4,9 @@ A plain, slow, single-threaded FP64 C implementation (``oracle.c``) of what
 the parallel loop computes: the global assembly sums of the Helmholtz-type
 bilinear form, the source linear form and the matrix-free action, with its own
 sparsity; and the nonlinear residual kappa grad(u).grad(v) + u^3 v - f v with
-its vector-Jacobian products (the adjoint assembly).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+its vector-Jacobian products (the adjoint assembly); and vector Lagrange
+linear elasticity 2 mu eps(u):eps(v) + lam div(u) div(v) on per-cell
+coordinates (the precision benchmark).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The product library never does.
 
 Every function here follows the paper's definition of a parallel loop over
@@ -69,6 +71,12 @@ def lib():
         L.oracle_nl_residual.restype = I
         L.oracle_nl_adjoint.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P, P, P]
         L.oracle_nl_adjoint.restype = I
+        L.oracle_elasticity_element.argtypes = [I, I, P, P, P, P, P]
+        L.oracle_elasticity_element.restype = I
+        L.oracle_elasticity_mat.argtypes = [I, I, L64, P, P, P, P, P, P, P, L64, P, P]
+        L.oracle_elasticity_mat.restype = I
+        L.oracle_elasticity_rows.argtypes = [I, I, L64, P, P, P, P, P, L64, L64, P, L64, P, P, P, P]
+        L.oracle_elasticity_rows.restype = L64
         _lib = L
     return _lib
 
@@ -265,3 +273,50 @@ def nl_adjoint(dim, cell_vertex, coords, cell_node, u, kappa, lam, nnodes):
     if rc:
         raise RuntimeError(f"oracle nl_adjoint failed ({rc})")
     return gu, gua, gk, gka
+
+
+def vector_map(cell_node, dim):
+    """Cell-to-DOF Map of the vector space: DOF dim*node + a, local (i, a) at i*dim + a."""
+    cn = np.asarray(cell_node, dtype=np.int64)
+    return np.ascontiguousarray((dim * cn[:, :, None] + np.arange(dim)).reshape(cn.shape[0], -1)
+                                .astype(np.int32))
+
+
+def elasticity_element(dim, degree, xv, muv, lav):
+    """Element matrix [dim*n][dim*n] (row (i, a) = i*dim + a) and its magnitude scale."""
+    xv = _c(xv, np.float64); muv = _c(muv, np.float64); lav = _c(lav, np.float64)
+    N = dim * nloc(dim, degree)
+    A = np.zeros((N, N)); Aa = np.zeros((N, N))
+    if lib().oracle_elasticity_element(dim, degree, _p(xv), _p(muv), _p(lav), _p(A), _p(Aa)):
+        raise RuntimeError("oracle elasticity_element failed")
+    return A, Aa
+
+
+def elasticity_mat(dim, degree, cell_vertex, xdg, cell_node, mu, lam, row_ptr, col_idx):
+    """Global elasticity matrix on the vector CSR (row_ptr, col_idx); xdg [C][dim+1][dim]."""
+    cv = _c(cell_vertex, np.int32); X = _c(xdg, np.float64); cn = _c(cell_node, np.int32)
+    m = _c(mu, np.float64); la = _c(lam, np.float64); rp = _c(row_ptr, np.int64); ci = _c(col_idx, np.int32)
+    nrows = rp.size - 1
+    vals = np.zeros(max(int(rp[-1]), 1)); absv = np.zeros_like(vals)
+    rc = lib().oracle_elasticity_mat(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(m), _p(la),
+                                     _p(rp), _p(ci), nrows, _p(vals), _p(absv))
+    if rc:
+        raise RuntimeError(f"oracle elasticity_mat failed ({rc})")
+    nnz = int(rp[-1])
+    return vals[:nnz], absv[:nnz]
+
+
+def elasticity_rows(dim, degree, cell_vertex, xdg, cell_node, mu, lam, nrows, rows):
+    """Assembled vector rows ``rows`` (distinct): list of (cols, vals, abs) per row."""
+    cv = _c(cell_vertex, np.int32); X = _c(xdg, np.float64); cn = _c(cell_node, np.int32)
+    m = _c(mu, np.float64); la = _c(lam, np.float64); rows = _c(rows, np.int64)
+    cap = rows.size * 1024
+    ptr = np.zeros(rows.size + 1, dtype=np.int64)
+    cols = np.zeros(cap, dtype=np.int32); vals = np.zeros(cap); absv = np.zeros(cap)
+    tot = lib().oracle_elasticity_rows(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(m), _p(la),
+                                       nrows, rows.size, _p(rows), cap, _p(ptr), _p(cols), _p(vals),
+                                       _p(absv))
+    if tot < 0:
+        raise RuntimeError(f"oracle elasticity_rows failed ({tot})")
+    return [(cols[ptr[s]:ptr[s + 1]].copy(), vals[ptr[s]:ptr[s + 1]].copy(),
+             absv[ptr[s]:ptr[s + 1]].copy()) for s in range(rows.size)]

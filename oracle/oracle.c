@@ -814,3 +814,185 @@ int oracle_nl_adjoint(int dim, int64_t ncells, const int32_t *cell_vertex, const
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Vector Lagrange linear elasticity (the precision benchmark)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * a(u, v) = integral of 2 mu eps(u):eps(v) + lam div(u) div(v), with eps the
+ * symmetric gradient and mu, lam P1 fields.  u and v lie in the vector
+ * Lagrange space of the given degree with dim components; with the basis
+ * phi_i e_a (DOF dim*node + a, node-major) the entry is
+ *
+ *   A[(i,a),(j,b)] = integral of  mu (delta_ab grad phi_i . grad phi_j
+ *                                     + d_b phi_i d_a phi_j)
+ *                                + lam d_a phi_i d_b phi_j,
+ *
+ * because 2 eps(phi_j e_b):eps(phi_i e_a) = delta_ab grad phi_i . grad phi_j
+ * + d_b phi_i d_a phi_j and div(phi e_b) = d_b phi.  The integrand has degree
+ * 2 degree - 1 on affine cells.  A is [dim*n][dim*n], row (i, a) = i*dim + a;
+ * Aabs sums the magnitudes of the terms (the rounding scale of each entry).
+ * xv: the cell's vertex coordinates [dim+1][dim]; muv, lav: mu and lam at the
+ * vertices.
+ */
+int oracle_elasticity_element(int dim, int degree, const double *xv, const double *muv, const double *lav,
+                              double *A, double *Aabs)
+{
+    const int n = oracle_nloc(dim, degree), nv = dim + 1, N = dim * n;
+    if (n < 0) return -1;
+    struct rule R;
+    if (make_rule(dim, 2 * degree - 1, &R)) return -1;
+    double J[9], Jinv[9];
+    const double adet = fabs(cell_geometry(dim, xv, J, Jinv));
+    memset(A, 0, sizeof(double) * N * N);
+    if (Aabs) memset(Aabs, 0, sizeof(double) * N * N);
+    for (int p = 0; p < R.np; ++p) {
+        double lam[4], phi[MAXLOC], gphi[MAXLOC * 3];
+        eval_at_point(dim, degree, xv, Jinv, &R.pts[p * dim], lam, phi, gphi);
+        double mu = 0.0, la = 0.0;
+        for (int m = 0; m < nv; ++m) { mu += muv[m] * lam[m]; la += lav[m] * lam[m]; }
+        const double w = R.wts[p] * adet;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double g = 0.0, ga = 0.0;
+                for (int r = 0; r < dim; ++r) {
+                    g += gphi[i * dim + r] * gphi[j * dim + r];
+                    ga += fabs(gphi[i * dim + r] * gphi[j * dim + r]);
+                }
+                for (int a = 0; a < dim; ++a)
+                    for (int b = 0; b < dim; ++b) {
+                        const double cross = gphi[i * dim + b] * gphi[j * dim + a];
+                        const double dd = gphi[i * dim + a] * gphi[j * dim + b];
+                        const double t = mu * ((a == b ? g : 0.0) + cross) + la * dd;
+                        const int64_t k = (int64_t)(i * dim + a) * N + (j * dim + b);
+                        A[k] += w * t;
+                        if (Aabs)
+                            Aabs[k] += fabs(w) * (fabs(mu) * ((a == b ? ga : 0.0) + fabs(cross)) + fabs(la * dd));
+                    }
+            }
+    }
+    return 0;
+}
+
+/*
+ * Global elasticity matrix.  Coordinates are per cell: xdg[c][m][r] (a
+ * discontinuous coordinate field); mu and lam are vertex fields read through
+ * cell_vertex; cell_node is the scalar node Map, vector DOFs are dim*node + a.
+ * row_ptr/col_idx: the vector CSR (rows dim*nnodes).  Cells in index order,
+ * each contribution found by binary search in its row.
+ */
+int oracle_elasticity_mat(int dim, int degree, int64_t ncells, const int32_t *cell_vertex,
+                          const double *xdg, const int32_t *cell_node, const double *mu, const double *lam,
+                          const int64_t *row_ptr, const int32_t *col_idx, int64_t nrows, double *values,
+                          double *absval)
+{
+    const int n = oracle_nloc(dim, degree), nv = dim + 1, N = dim * n;
+    if (n < 0) return -1;
+    const int64_t nnz = row_ptr[nrows];
+    memset(values, 0, sizeof(double) * (size_t)nnz);
+    if (absval) memset(absval, 0, sizeof(double) * (size_t)nnz);
+    double *A = malloc(sizeof(double) * N * N), *Aa = malloc(sizeof(double) * N * N);
+    if (!A || !Aa) { free(A); free(Aa); return -1; }
+    double muv[4], lav[4];
+    int rc = 0;
+    for (int64_t c = 0; c < ncells && !rc; ++c) {
+        for (int m = 0; m < nv; ++m) {
+            muv[m] = mu[cell_vertex[c * nv + m]];
+            lav[m] = lam[cell_vertex[c * nv + m]];
+        }
+        if (oracle_elasticity_element(dim, degree, xdg + c * nv * dim, muv, lav, A, Aa)) { rc = -1; break; }
+        for (int i = 0; i < n && !rc; ++i)
+            for (int a = 0; a < dim && !rc; ++a) {
+                const int64_t r = (int64_t)dim * cell_node[c * n + i] + a;
+                if (r < 0 || r >= nrows) { rc = -2; break; }
+                for (int j = 0; j < n; ++j)
+                    for (int b = 0; b < dim; ++b) {
+                        const int64_t k = find_col(row_ptr, col_idx, r, dim * cell_node[c * n + j] + b);
+                        if (k < 0) { rc = -3; break; }
+                        values[k] += A[(int64_t)(i * dim + a) * N + j * dim + b];
+                        if (absval) absval[k] += Aa[(int64_t)(i * dim + a) * N + j * dim + b];
+                    }
+            }
+    }
+    free(A); free(Aa);
+    return rc;
+}
+
+/*
+ * Selected rows of the global elasticity matrix (vector DOF rows, distinct),
+ * for meshes too large to assemble whole; same output convention as
+ * oracle_mat_rows.
+ */
+int64_t oracle_elasticity_rows(int dim, int degree, int64_t ncells, const int32_t *cell_vertex,
+                               const double *xdg, const int32_t *cell_node, const double *mu,
+                               const double *lam, int64_t nrows, int64_t nsel, const int64_t *rows,
+                               int64_t cap, int64_t *out_ptr, int32_t *out_cols, double *out_vals,
+                               double *out_abs)
+{
+    const int n = oracle_nloc(dim, degree), nv = dim + 1, N = dim * n;
+    if (n < 0) return -1;
+    const int64_t per = 1024;
+    int64_t *slot = malloc(sizeof(int64_t) * (size_t)nrows);
+    int32_t *cols = malloc(sizeof(int32_t) * (size_t)(nsel * per));
+    double *vals = calloc((size_t)(nsel * per), sizeof(double));
+    double *abss = calloc((size_t)(nsel * per), sizeof(double));
+    int64_t *cnt = calloc((size_t)nsel, sizeof(int64_t));
+    double *A = malloc(sizeof(double) * N * N), *Aa = malloc(sizeof(double) * N * N);
+    int64_t rc = 0;
+    if (!slot || !cols || !vals || !abss || !cnt || !A || !Aa) rc = -1;
+    if (!rc) {
+        for (int64_t r = 0; r < nrows; ++r) slot[r] = -1;
+        for (int64_t s = 0; s < nsel; ++s) slot[rows[s]] = s;
+    }
+    double muv[4], lav[4];
+    for (int64_t c = 0; c < ncells && rc == 0; ++c) {
+        int any = 0;
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < dim; ++a) any |= slot[(int64_t)dim * cell_node[c * n + i] + a] >= 0;
+        if (!any) continue;
+        for (int m = 0; m < nv; ++m) {
+            muv[m] = mu[cell_vertex[c * nv + m]];
+            lav[m] = lam[cell_vertex[c * nv + m]];
+        }
+        oracle_elasticity_element(dim, degree, xdg + c * nv * dim, muv, lav, A, Aa);
+        for (int i = 0; i < n && rc == 0; ++i)
+            for (int a = 0; a < dim && rc == 0; ++a) {
+                const int64_t s = slot[(int64_t)dim * cell_node[c * n + i] + a];
+                if (s < 0) continue;
+                for (int j = 0; j < n; ++j)
+                    for (int b = 0; b < dim; ++b) {
+                        const int32_t col = dim * cell_node[c * n + j] + b;
+                        int64_t k = 0;
+                        while (k < cnt[s] && cols[s * per + k] != col) ++k;
+                        if (k == cnt[s]) {
+                            if (k == per) { rc = -4; break; }
+                            cols[s * per + k] = col; cnt[s]++;
+                        }
+                        vals[s * per + k] += A[(int64_t)(i * dim + a) * N + j * dim + b];
+                        abss[s * per + k] += Aa[(int64_t)(i * dim + a) * N + j * dim + b];
+                    }
+            }
+    }
+    int64_t total = 0;
+    if (rc == 0) {
+        out_ptr[0] = 0;
+        for (int64_t s = 0; s < nsel; ++s) {
+            int32_t *cc = cols + s * per; double *vv = vals + s * per, *aa = abss + s * per;
+            for (int64_t a = 1; a < cnt[s]; ++a) {
+                int32_t kc = cc[a]; double kv2 = vv[a], ka = aa[a];
+                int64_t b = a - 1;
+                while (b >= 0 && cc[b] > kc) { cc[b + 1] = cc[b]; vv[b + 1] = vv[b]; aa[b + 1] = aa[b]; --b; }
+                cc[b + 1] = kc; vv[b + 1] = kv2; aa[b + 1] = ka;
+            }
+            if (total + cnt[s] > cap) { rc = -5; break; }
+            memcpy(out_cols + total, cc, sizeof(int32_t) * (size_t)cnt[s]);
+            memcpy(out_vals + total, vv, sizeof(double) * (size_t)cnt[s]);
+            memcpy(out_abs + total, aa, sizeof(double) * (size_t)cnt[s]);
+            total += cnt[s];
+            out_ptr[s + 1] = total;
+        }
+    }
+    free(slot); free(cols); free(vals); free(abss); free(cnt); free(A); free(Aa);
+    return rc ? rc : total;
+}
