@@ -30,6 +30,11 @@
  *                  P1 only; u, kappa, f are P1 fields on the nodes; its
  *                  vector-Jacobian products come from
  *                  fem_par_loop_assemble_adjoint)
+ *   FEM_ELASTICITY 2 mu eps(u):eps(v) + lam div(u) div(v)   (linear
+ *                  elasticity, eps the symmetric gradient; vector P2 on
+ *                  tetrahedra, form dim 3; mu, lam P1 fields; the element
+ *                  contraction may run in FP32, BF16 or FP16 on the matrix
+ *                  cores, geometry and the global sums stay FP64)
  *
  * Memory, ownership, ordering
  *   - Every pointer inside fem_map, fem_dat, fem_sparsity and fem_mat is a
@@ -90,14 +95,20 @@ typedef enum fem_access { FEM_READ = 0, FEM_WRITE = 1, FEM_INC = 2 } fem_access;
 
 typedef enum fem_cell { FEM_TRIANGLE = 2, FEM_TETRAHEDRON = 3 } fem_cell;
 
-/* Arithmetic of the local kernel.  FEM_FP64 everywhere; FEM_FP32 for
- * FEM_NL_RESIDUAL (its residual and adjoint: geometry, element values and
- * the per-row sums in binary32, results stored as float64); the others
- * return FEM_E_UNSUPPORTED. */
+/* Arithmetic of the local kernel.  FEM_FP64 everywhere.  FEM_FP32 for
+ * FEM_NL_RESIDUAL (its residual and adjoint: element values and the per-row
+ * sums in binary32 after FP64 edge vectors, results stored as float64).
+ * FEM_FP32, FEM_BF16, FEM_FP16 for FEM_ELASTICITY: the operands of the
+ * element contraction (the reference tensor and the per-cell geometry
+ * factor, scaled per cell by a power of two) are rounded to that type and
+ * multiplied on the matrix cores with FP32 accumulation; the Jacobian, its
+ * determinant and inverse are FP64 for every cell, and the global sums are
+ * FP64.  Other combinations return FEM_E_UNSUPPORTED. */
 typedef enum fem_prec { FEM_FP64 = 0, FEM_FP32 = 1, FEM_BF16 = 2, FEM_FP16 = 3 } fem_prec;
 
 typedef enum fem_kind {
-    FEM_MASS = 0, FEM_LAPLACE = 1, FEM_HELMHOLTZ = 2, FEM_SOURCE = 3, FEM_NL_RESIDUAL = 4
+    FEM_MASS = 0, FEM_LAPLACE = 1, FEM_HELMHOLTZ = 2, FEM_SOURCE = 3, FEM_NL_RESIDUAL = 4,
+    FEM_ELASTICITY = 5
 } fem_kind;
 
 /* A Set: only a size ("Sets"). */
@@ -136,8 +147,8 @@ typedef struct fem_mat {
 } fem_mat;
 
 /* The local kernel: form kind, cell shape, Lagrange degree of the test and
- * trial space (1..3), value dimension of that space (1), contraction
- * precision. */
+ * trial space (1..3), value dimension of that space (1; 3 for
+ * FEM_ELASTICITY), contraction precision. */
 typedef struct fem_form {
     fem_kind kind;
     fem_cell cell;
@@ -153,7 +164,14 @@ typedef struct fem_form {
  * is kappa for the bilinear forms and f for FEM_SOURCE.  For
  * FEM_NL_RESIDUAL they are fields of the P1 space itself, on the node Set,
  * read through cell_node: coeff[0] = u, coeff[1] = kappa, coeff[2] = f (f is
- * not read by the adjoint). */
+ * not read by the adjoint).  For FEM_ELASTICITY coeff[0] = mu and coeff[1] =
+ * lam (P1, through cell_vertex), and the coordinates are read through
+ * cell_coord.  cell_coord: optional Map from the cells to the Set that
+ * coords lives on (arity d+1); NULL means coords is a vertex Dat read
+ * through cell_vertex.  FEM_ELASTICITY requires it, so that the coordinate
+ * field may be discontinuous (per cell) and single cells may be reshaped
+ * without moving their neighbours (coordinates are an ordinary field, "The
+ * mesh abstraction"). */
 typedef struct fem_args {
     const fem_set *cells;
     const fem_map *cell_vertex;
@@ -161,6 +179,7 @@ typedef struct fem_args {
     const fem_map *cell_node;
     const fem_dat *coeff[4];
     int32_t ncoeff;
+    const fem_map *cell_coord;
 } fem_args;
 
 typedef struct fem_ctx fem_ctx;
@@ -194,6 +213,21 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
                               fem_sparsity *sp);
 
 /*
+ * Sparsity of a vector-valued space from the node sparsity: every node entry
+ * (n, m) becomes the bs x bs block of rows bs*n + a, columns bs*m + b
+ * (node-major DOFs, "Function spaces and functions": the vector CSR is the
+ * node CSR with each entry replaced by a dense block).  Row bs*n + a holds
+ * bs * len(n) columns in ascending order.  Two calls, like
+ * fem_build_sparsity:
+ *   1. out->col_idx == NULL: writes out->row_ptr (caller-allocated,
+ *      bs*node->nrows + 1) and sets out->nrows, ncols, nnz (= bs^2 node->nnz).
+ *   2. out->col_idx != NULL (out->nnz entries): fills the columns.
+ * node is a CSR built by fem_build_sparsity.  bs in 1..8.  FEM_E_OVERFLOW if
+ * bs * ncols exceeds int32.  Neither call synchronises or allocates.
+ */
+fem_status fem_expand_sparsity(fem_ctx *ctx, const fem_sparsity *node, int32_t bs, fem_sparsity *out);
+
+/*
  * Execution plan of the deterministic INC for one (form, args) pair.
  * With sp != NULL the plan serves fem_par_loop_assemble_mat on that
  * sparsity; with sp == NULL it serves fem_par_loop_assemble_vec and
@@ -203,6 +237,14 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
  * atomics; "Access descriptors": only INC needs a schedule).  It references
  * the Maps' device arrays: rebuild it if their contents change.  Synchronises;
  * allocates device memory owned by the plan.
+ *
+ * FEM_ELASTICITY plans (sp = the vector CSR, the 3x3-block expansion of the
+ * node sparsity, e.g. from fem_expand_sparsity) hold, per node pair, the
+ * list of its (cell, local pair) contributions in ascending cell id, and a
+ * workspace for the element blocks of every cell ([cells][55][9] values of
+ * float64 for FEM_FP64, float32 otherwise).  Assembly calls on one plan
+ * share that workspace: they must not overlap in time (queue them on one
+ * stream).  FEM_E_OVERFLOW for 2^24 cells or more.
  */
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
                            const fem_sparsity *sp, fem_plan **plan);
@@ -216,7 +258,10 @@ fem_status fem_plan_info(const fem_plan *plan, int64_t *nblocks, int64_t *cell_v
  * A[rmap(c,i), cmap(c,j)] (+)= integral over cell c of the bilinear form, for
  * every cell c (par_loop with the Mat argument INC'd through two Maps).
  * acc = FEM_WRITE overwrites A->values with the sum, FEM_INC adds to them.
- * Asynchronous on the context stream; allocates nothing.
+ * Asynchronous on the context stream; allocates nothing.  FEM_ELASTICITY
+ * runs two kernels: the element blocks into the plan's workspace (matrix
+ * cores, the form's precision), then the FP64 sums into A in ascending cell
+ * order per value.
  */
 fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
                                      const fem_args *args, fem_mat *A, fem_access acc);

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfem.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip"]
+SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip", "fem_elast.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,6 +38,9 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_tables.py"),
                            os.path.join(CSRC, "fem_tables.h")],
+                          stdout=subprocess.DEVNULL)
+    subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_elast_tables.py"),
+                           os.path.join(CSRC, "fem_elast_tables.h")],
                           stdout=subprocess.DEVNULL)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -69,6 +69,11 @@ struct DevBuf {
 fem_status check_form(fem_ctx *ctx, const fem_form *f)
 {
     if (!f) return fail(ctx, FEM_E_ARG, "form is NULL");
+    if (f->kind == FEM_ELASTICITY) {
+        if (f->prec < FEM_FP64 || f->prec > FEM_FP16)
+            return fail(ctx, FEM_E_UNSUPPORTED, "precision %d not supported", (int)f->prec);
+        return FEM_OK;   // shape, degree and value dimension: femk::elast_check
+    }
     if (f->cell != FEM_TRIANGLE && f->cell != FEM_TETRAHEDRON)
         return fail(ctx, FEM_E_UNSUPPORTED, "cell %d not supported", (int)f->cell);
     if (f->degree < 1 || f->degree > 3)
@@ -88,6 +93,8 @@ fem_status check_args(fem_ctx *ctx, const fem_form *f, const fem_args *a, bool n
 {
     if (!a || !a->cells || !a->cell_vertex || !a->coords || !a->cell_node)
         return fail(ctx, FEM_E_ARG, "args: cells, cell_vertex, coords and cell_node are required");
+    if (a->cell_coord)
+        return fail(ctx, FEM_E_UNSUPPORTED, "args: a separate coordinate Map is provided for FEM_ELASTICITY only");
     const int d = (int)f->cell;
     const int nl = nloc_of(d, f->degree);
     if (!map_ok(a->cell_vertex) || !map_ok(a->cell_node))
@@ -134,7 +141,8 @@ fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *n
 void free_plan_arrays(fem_plan *p)
 {
     void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
-                    p->blk_hdr, p->blk_w, p->wq, p->pstream};
+                    p->blk_hdr, p->blk_w, p->wq, p->pstream,
+                    p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }
@@ -339,6 +347,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     *out = nullptr;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
+    if (form->kind == FEM_ELASTICITY) return femk::elast_plan_create(ctx, form, args, sp, out);
     st = check_args(ctx, form, args, false);
     if (st != FEM_OK) return st;
     const bool is_mat = sp != nullptr;
@@ -706,6 +715,7 @@ fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const f
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
+    if (form->kind == FEM_ELASTICITY) return femk::elast_assemble(ctx, plan, form, args, A, acc);
     if (form->kind == FEM_SOURCE || form->kind == FEM_NL_RESIDUAL)
         return fail(ctx, FEM_E_ARG, "assemble_mat needs a bilinear form");
     const bool need_k = form->kind != FEM_MASS;
@@ -774,6 +784,8 @@ fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *
     if (st != FEM_OK) return st;
     if (form->kind == FEM_SOURCE || form->kind == FEM_NL_RESIDUAL)
         return fail(ctx, FEM_E_ARG, "apply_action needs a bilinear form");
+    if (form->kind == FEM_ELASTICITY)
+        return fail(ctx, FEM_E_UNSUPPORTED, "apply_action: no matrix-free elasticity kernel");
     const bool need_k = form->kind != FEM_MASS;
     if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
     if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
@@ -836,6 +848,8 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);
     if (st != FEM_OK) return st;
+    if (form->kind == FEM_ELASTICITY)
+        return fail(ctx, FEM_E_UNSUPPORTED, "renumber: use the scalar form of the same space");
     if ((st = check_args(ctx, form, args, false)) != FEM_OK) return st;
     const int dim = (int)form->cell, deg = form->degree, nl = nloc_of(dim, deg), nv = dim + 1;
     const int64_t ncells = args->cells->size, nverts = args->cell_vertex->to->size,

@@ -46,6 +46,16 @@ struct fem_plan {
     int64_t stream_entries = 0;  // Mat plans: 16-bit stream entries (padding included)
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
     int32_t max_blk_cells = 0;   // most cells any block gathers
+    // Elasticity plans (is_mat == 2): per node pair of the node sparsity (a
+    // 3x3 block of the vector CSR), its contributions in ascending cell id,
+    // and the element-block workspace [ncells][55][9] (float64 for FEM_FP64,
+    // float32 otherwise).
+    int32_t *e_slot_ptr = nullptr;  // [nslots+1]
+    uint32_t *e_ent = nullptr;      // (cell << 8) | (pair << 2) | (diagonal << 1) | transposed
+    int32_t *e_grow = nullptr;      // [nslots/64 + 1] node row of slot 64 g
+    void *e_work = nullptr;
+    int64_t e_nslots = 0;
+    int e_prec = 0;
     size_t bytes = 0;            // device bytes held
     // device arrays (owned)
     int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
@@ -102,6 +112,14 @@ hipError_t launch_action(const AsmArgs &a, hipStream_t s);
 // lambda = aux; 3: both, into out and out2); P1 Dat plans; fp32 selects
 // binary32 arithmetic.
 hipError_t launch_nl(const AsmArgs &a, int mode, bool fp32, hipStream_t s);
+
+// Vector P2 linear elasticity (fem_elast.hip): argument checks, plan and
+// assembly (element blocks by MFMA, then the pull into the CSR).
+fem_status elast_check(fem_ctx *ctx, const fem_form *form, const fem_args *args);
+fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args, const fem_sparsity *sp,
+                             fem_plan **out);
+fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                          fem_mat *A, fem_access acc);
 
 // Per-(dim, degree) launch limits used by the plan builder.
 struct Limits {

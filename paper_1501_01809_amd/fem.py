@@ -21,10 +21,11 @@ STATUS_NAMES = {0: "FEM_OK", 1: "FEM_E_ARG", 2: "FEM_E_RANGE", 3: "FEM_E_OVERFLO
 FEM_READ, FEM_WRITE, FEM_INC = 0, 1, 2
 FEM_TRIANGLE, FEM_TETRAHEDRON = 2, 3
 FEM_FP64, FEM_FP32, FEM_BF16, FEM_FP16 = 0, 1, 2, 3
-FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE, FEM_NL_RESIDUAL = 0, 1, 2, 3, 4
+FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE, FEM_NL_RESIDUAL, FEM_ELASTICITY = 0, 1, 2, 3, 4, 5
 
 KINDS = {"mass": FEM_MASS, "laplace": FEM_LAPLACE, "helmholtz": FEM_HELMHOLTZ, "source": FEM_SOURCE,
-         "nl_residual": FEM_NL_RESIDUAL}
+         "nl_residual": FEM_NL_RESIDUAL, "elasticity": FEM_ELASTICITY}
+PRECS = {"fp64": FEM_FP64, "fp32": FEM_FP32, "bf16": FEM_BF16, "fp16": FEM_FP16}
 
 
 class FemError(RuntimeError):
@@ -63,13 +64,14 @@ class fem_form(C.Structure):
 class fem_args(C.Structure):
     _fields_ = [("cells", C.POINTER(fem_set)), ("cell_vertex", C.POINTER(fem_map)),
                 ("coords", C.POINTER(fem_dat)), ("cell_node", C.POINTER(fem_map)),
-                ("coeff", C.POINTER(fem_dat) * 4), ("ncoeff", C.c_int32)]
+                ("coeff", C.POINTER(fem_dat) * 4), ("ncoeff", C.c_int32),
+                ("cell_coord", C.POINTER(fem_map))]
 
 
 EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_error", "fem_sync",
            "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
-           "fem_par_loop_assemble_adjoint", "fem_renumber"]
+           "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity"]
 
 _lib = None
 
@@ -102,6 +104,7 @@ def lib():
                                                     C.POINTER(fem_dat), C.POINTER(fem_dat), C.POINTER(fem_dat),
                                                     C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
+        L.fem_expand_sparsity.argtypes = [P, C.POINTER(fem_sparsity), C.c_int32, C.POINTER(fem_sparsity)]
         for name in EXPORTS:
             if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -153,10 +156,12 @@ def form(kind="helmholtz", cell=3, degree=1, dim=1, prec=FEM_FP64):
 class Args:
     """par_loop arguments over torch device tensors (references kept alive)."""
 
-    def __init__(self, cell_vertex, coords, cell_node, nnodes, coeffs=(), nodal=False):
+    def __init__(self, cell_vertex, coords, cell_node, nnodes, coeffs=(), nodal=False, cell_coord=None):
         """coeffs: float64 tensors, on the vertex Set (P1 fields read through
         cell_vertex) or, with nodal=True, on the node Set (the nonlinear
-        residual's u, kappa, f)."""
+        residual's u, kappa, f).  cell_coord: optional int32 [cells][d+1]
+        Map to the Set of coords' rows (a per-cell coordinate field for
+        FEM_ELASTICITY); without it coords are read through cell_vertex."""
         import torch
         assert cell_vertex.dtype == torch.int32 and cell_node.dtype == torch.int32
         assert coords.dtype == torch.float64
@@ -168,7 +173,14 @@ class Args:
         self.nodes = fem_set(nnodes)
         self.cv = fem_map(C.pointer(self.cells), C.pointer(self.verts), cell_vertex.shape[1], _ptr(cell_vertex))
         self.cn = fem_map(C.pointer(self.cells), C.pointer(self.nodes), cell_node.shape[1], _ptr(cell_node))
-        self.X = fem_dat(C.pointer(self.verts), coords.shape[1], _ptr(coords))
+        self.cell_coord = cell_coord
+        if cell_coord is not None:
+            assert cell_coord.dtype == torch.int32
+            self.cset = fem_set(coords.shape[0])
+            self.cc = fem_map(C.pointer(self.cells), C.pointer(self.cset), cell_coord.shape[1], _ptr(cell_coord))
+            self.X = fem_dat(C.pointer(self.cset), coords.shape[1], _ptr(coords))
+        else:
+            self.X = fem_dat(C.pointer(self.verts), coords.shape[1], _ptr(coords))
         cset = self.nodes if nodal else self.verts
         self.cdats = [fem_dat(C.pointer(cset), 1, _ptr(c)) for c in self.coeffs]
         self.c = fem_args()
@@ -179,9 +191,12 @@ class Args:
         for i, d in enumerate(self.cdats):
             self.c.coeff[i] = C.pointer(d)
         self.c.ncoeff = len(self.cdats)
+        if cell_coord is not None:
+            self.c.cell_coord = C.pointer(self.cc)
 
     def with_coeffs(self, *coeffs, nodal=False):
-        return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs, nodal)
+        return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs, nodal,
+                    self.cell_coord)
 
 
 class Sparsity:
@@ -223,6 +238,18 @@ def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | N
     sp.col_idx = C.c_void_p(col_idx.data_ptr())
     ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp)))
     return Sparsity(row_ptr, col_idx[:sp.nnz], nrows, ncols)
+
+
+def fem_expand_sparsity(ctx: Context, sp: Sparsity, bs: int) -> Sparsity:
+    """The bs x bs block expansion of a node CSR (vector DOF bs*node + a)."""
+    import torch
+    row_ptr = torch.empty(bs * sp.c.nrows + 1, dtype=torch.int64, device=sp.row_ptr.device)
+    out = fem_sparsity(0, 0, 0, _ptr(row_ptr), None)
+    ctx.check(lib().fem_expand_sparsity(ctx.h, C.byref(sp.c), bs, C.byref(out)))
+    col_idx = torch.empty(max(out.nnz, 1), dtype=torch.int32, device=sp.row_ptr.device)
+    out.col_idx = C.c_void_p(col_idx.data_ptr())
+    ctx.check(lib().fem_expand_sparsity(ctx.h, C.byref(sp.c), bs, C.byref(out)))
+    return Sparsity(row_ptr, col_idx[:out.nnz], out.nrows, out.ncols)
 
 
 def fem_plan_create(ctx: Context, frm: fem_form, args: Args, sp: Sparsity | None = None) -> Plan:
