@@ -202,6 +202,77 @@ def bench_nl(ctx, steps: int, warmup: int, seed: int, n: int = 512):
     return out
 
 
+def bench_precision(ctx, steps: int, warmup: int, seed: int, n: int = 48):
+    """The precision workload: vector P2 linear elasticity
+    2 mu eps(u):eps(v) + lam div u div v on n^3 x 6 Kuhn tetrahedra jittered by
+    U[-0.2h, 0.2h], per-cell coordinates with 1% of the cells flattened to
+    aspect ratio ~1e3, mu and lam P1 U[0.5, 2]; CSR assembly (WRITE) with the
+    element contraction in FP64, FP32, BF16 and FP16 (FP64 geometry and
+    global sums).  Timed per call (element kernel + pull) with HIP events."""
+    import torch
+    import fem_inputs as fi
+    from paper_1501_01809_amd import fem as F
+    dev = torch.device("cuda:0")
+    st = fi.spawn_streams(seed)
+    m = fi.jitter_interior(fi.unit_cube(n), 0.2, st["mesh"])
+    xdg, chosen = fi.flatten_cells(fi.dg_coordinates(m), 0.01, st["flatten"])
+    cn, N = fi.node_map(m, 2)
+    mu = fi.field(st["mu"], m.nverts, 0.5, 2.0)
+    lam = fi.field(st["lam"], m.nverts, 0.5, 2.0)
+    C = m.ncells
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    # Hilbert renumbering of cells, vertices and nodes (through the scalar P2
+    # form on the continuous mesh), as for the other workloads
+    t0 = time.perf_counter()
+    cells = m.cells.astype(np.int32); cn = cn.astype(np.int32)
+    cp, vp, npn = F.fem_renumber(ctx, F.form("helmholtz", 3, 2),
+                                 F.Args(t(cells), t(m.coords), t(cn), N, [t(mu)]))
+    vinv = np.empty_like(vp); vinv[vp] = np.arange(vp.size, dtype=vp.dtype)
+    ninv = np.empty_like(npn); ninv[npn] = np.arange(npn.size, dtype=npn.dtype)
+    cells = vinv[cells[cp]].astype(np.int32); cn = ninv[cn[cp]].astype(np.int32)
+    xdg = xdg[cp]; mu = mu[vp]; lam = lam[vp]
+    renumber_ms = (time.perf_counter() - t0) * 1e3
+    g_cv, g_cn, g_X = t(cells), t(cn), t(xdg.reshape(-1, 3))
+    g_cc = t(np.arange(4 * C, dtype=np.int32).reshape(C, 4))
+    args = F.Args(g_cv, g_X, g_cn, N, [t(mu), t(lam)], cell_coord=g_cc)
+    t0 = time.perf_counter()
+    sp = F.fem_expand_sparsity(ctx, F.fem_build_sparsity(ctx, g_cn, N), 3)
+    torch.cuda.synchronize()
+    setup = {"renumber_ms": renumber_ms, "sparsity_ms": (time.perf_counter() - t0) * 1e3}
+    nnz = int(sp.col_idx.numel())
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    V = m.nverts
+    alg = C * (4 * 10 + 4 * 4 + 4 * 4) + C * 4 * 3 * 8 + V * 16 + (3 * N + 1) * 8 + 4 * nnz + 8 * nnz
+    out = {"workload": f"vector P2 elasticity on the unit cube, {n}^3x6 Kuhn tets ({C} cells, {3 * N} DOFs, "
+                       f"nnz {nnz}), jitter 0.2h, {chosen.size} cells flattened to aspect ~1e3, mu, lam P1 "
+                       f"U[0.5,2], Hilbert-renumbered", "cells": C, "dofs": 3 * N, "nnz": nnz, "alg_bytes": alg,
+           "flop_per_cell": 2 * 55 * 9 * 36}
+    for name in ("fp64", "fp32", "bf16", "fp16"):
+        frm = F.form("elasticity", 3, 2, 3, F.PRECS[name])
+        t0 = time.perf_counter()
+        plan = F.fem_plan_create(ctx, frm, args, sp)
+        setup[f"plan_{name}_ms"] = (time.perf_counter() - t0) * 1e3
+        for _ in range(warmup):
+            F.fem_par_loop_assemble_mat(ctx, plan, frm, args, vals, sp)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            F.fem_par_loop_assemble_mat(ctx, plan, frm, args, vals, sp)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        out[name] = {"ms": float(ms.mean()), "ms_min": float(ms.min()), "cells_per_s": C / (ms.mean() * 1e-3),
+                     "GBps": alg / (ms.mean() * 1e-3) / 1e9,
+                     "hbm_frac": alg / (ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del plan
+    for name in ("fp32", "bf16", "fp16"):
+        out[name]["speedup_vs_fp64"] = out["fp64"]["ms"] / out[name]["ms"]
+    out["setup_ms"] = setup
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +288,8 @@ def main():
     ap.add_argument("--no-renumber", action="store_true")
     ap.add_argument("--no-nl", action="store_true",
                     help="skip the differentiation workload (residual and adjoint, 512x512x2 triangles)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision workload (vector P2 elasticity, 48^3x6, four precisions)")
     ap.add_argument("--ops", default="mat,vec,action",
                     help="operations run in a step (a subset is for profiling the kernels one by one; "
                          "the reported metric needs all three)")
@@ -364,6 +437,8 @@ def main():
     }
     if not args.no_nl:
         out["differentiation"] = bench_nl(ctx, args.steps, args.warmup, args.seed)
+    if not args.no_precision:
+        out["precision"] = bench_precision(ctx, args.steps, args.warmup, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C), dim)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]

@@ -270,7 +270,12 @@ __global__ __launch_bounds__(256) void k_elast_pull(const int64_t *__restrict__ 
                                                     const T *__restrict__ E, double *__restrict__ out, int64_t nslots,
                                                     int inc)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // XCD-grouped ranks: the 8 XCDs (blocks dealt round-robin) each take a
+    // contiguous range of slots, so the cells shared by neighbouring rows are
+    // read through one L2
+    const int64_t per = gridDim.x / 8;
+    const int64_t rank = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t e = rank * 256 + threadIdx.x;
     if (e >= nslots) return;
     int64_t n = grow[e >> 6];
     while (rp3[3 * (n + 1)] / 9 <= e) ++n;
@@ -285,14 +290,17 @@ __global__ __launch_bounds__(256) void k_elast_pull(const int64_t *__restrict__ 
         const T *blk = E + (size_t)(w >> 8) * BLK + ((w >> 2) & 63) * 9;
         T v[9];
 #pragma unroll
-        for (int u = 0; u < 9; ++u) v[u] = blk[u];
+        for (int q = 0; q < 9; ++q) v[q] = blk[q];
         const bool dg = (w >> 1) & 1, tr = w & 1;
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
             for (int y = 0; y < 3; ++y) {
-                const T s = dg ? v[x < y ? x * 3 + y : y * 3 + x] : (tr ? v[y * 3 + x] : v[x * 3 + y]);
-                acc[x * 3 + y] += (double)s;
+                // entry (x, y) of the block is v[x][y], or v[y][x] when
+                // transposed; on the diagonal the upper triangle serves both
+                // halves (bitwise symmetric sums)
+                const bool take_b = x > y ? (dg || tr) : (x < y ? (tr && !dg) : false);
+                acc[x * 3 + y] += (double)(take_b ? v[y * 3 + x] : v[x * 3 + y]);
             }
     }
 #pragma unroll
@@ -555,7 +563,7 @@ fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *fo
     EHIP(hipGetLastError(), "elasticity element launch");
     const int64_t ns = plan->e_nslots;
     if (ns == 0) return FEM_OK;
-    const int pg = (int)((ns + 255) / 256);
+    const int pg = (int)((ns + 255) / 256 + 7) / 8 * 8;   // a multiple of 8 (XCD-grouped ranks)
     if (form->prec == FEM_FP64)
         hipLaunchKernelGGL(k_elast_pull<double>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr, plan->e_ent,
                            plan->e_grow, (const double *)plan->e_work, A->values, ns, (int)(acc == FEM_INC));
