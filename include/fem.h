@@ -311,6 +311,55 @@ fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *
 fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args,
                         int32_t *cell_perm, int32_t *vertex_perm, int32_t *node_perm);
 
+/*
+ * Request server: continuous batching of assemblies and actions on resident
+ * models (the paper keeps data on the device across parallel loops; its fixed
+ * per-call overheads are what batching amortises, "Experiments").
+ *
+ * A model is a mesh with the FP64 Helmholtz form of some degree: args as for
+ * fem_plan_create with coeff[0] = kappa and coeff[1] = f (P1 vertex Dats).
+ * fem_server_add_model builds its sparsity and Mat and Dat plans once and
+ * keeps them resident (synchronises).  The caller's device arrays (Maps,
+ * coordinates, fields, action inputs) must outlive the server; the Set/Map/
+ * Dat descriptors are copied.
+ *
+ * A request is FEM_REQ_ASSEMBLE (the CSR matrix and the right-hand side
+ * integral of f v, WRITE) or FEM_REQ_ACTION (y = A x for the caller's x on the
+ * model's nodes).  Submitted requests queue in arrival order.
+ * fem_server_poll, which never blocks, retires requests whose work has
+ * finished and admits the queue head while one of the `slots` is free and the
+ * request's outputs fit the HBM budget (hbm_budget bytes for resident models
+ * plus outputs in flight).  An admitted request's output memory is allocated
+ * stream-ordered and its kernels are queued on its slot's stream, so requests
+ * admitted while others run overlap with them on the device.  Its outputs
+ * (device pointers from fem_server_result: CSR values in the model's
+ * sparsity order and the vector, or y) stay valid until fem_server_release
+ * returns their memory to the budget.  Results do not depend on the mix:
+ * each request's kernels read only its own inputs and sum in a fixed order,
+ * so they are bitwise the same alone and with any other requests in flight.
+ * `now` and `arrival_time` are the caller's clock (seconds); the server
+ * stamps admission and completion with the `now` of the poll that saw them.
+ * The server owns its slot streams (default priority); it restores the
+ * context's stream before returning.  One host thread drives a server.
+ */
+typedef struct fem_server fem_server;
+typedef enum fem_req_op { FEM_REQ_ASSEMBLE = 0, FEM_REQ_ACTION = 1 } fem_req_op;
+
+fem_status fem_server_create(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fem_server **server);
+void fem_server_destroy(fem_server *server);
+fem_status fem_server_add_model(fem_server *server, const fem_form *form, const fem_args *args,
+                                int32_t *model_id, int64_t *resident_bytes);
+fem_status fem_server_submit(fem_server *server, int32_t model, int32_t op, const double *x,
+                             double arrival_time, int64_t *request_id);
+fem_status fem_server_poll(fem_server *server, double now, int32_t *completed, int32_t *running,
+                           int32_t *queued);
+fem_status fem_server_result(fem_server *server, int64_t request_id, const double **values,
+                             const double **vec, double *t_admit, double *t_done);
+fem_status fem_server_release(fem_server *server, int64_t request_id);
+/* A resident model's sizes and its sparsity (device pointers owned by the server). */
+fem_status fem_server_model_info(const fem_server *server, int32_t model, int64_t *cells, int64_t *nrows,
+                                 int64_t *nnz, const int64_t **row_ptr, const int32_t **col_idx);
+
 #ifdef __cplusplus
 }
 #endif

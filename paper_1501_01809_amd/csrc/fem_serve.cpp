@@ -1,0 +1,330 @@
+// Request server: continuous batching of assemblies and actions on resident
+// models (C ABI in include/fem.h, "Request server").
+//
+// A model is a mesh with its form (Helmholtz, P_k, with the P1 fields kappa
+// and f) made resident once: its sparsity and its Mat and Dat plans live in
+// device memory for the server's lifetime (the paper keeps data on the
+// device between parallel loops and pays setup once; its fixed per-call
+// overheads are what batching amortises, "Experiments").
+//
+// Requests (an assembly: CSR matrix + right-hand side; or an action y = A x)
+// queue in arrival order.  fem_server_poll admits the queue head whenever a
+// slot is free and its output memory fits the budget; an admitted request's
+// kernels go onto its slot's stream, so requests that arrive while others
+// are running start at once and overlap on the device with them.  The poll
+// also retires requests whose completion event has fired.  Every kernel is
+// deterministic and reads only its own request's data, so a result is
+// bitwise the same alone and in any mix.
+#include <cstdarg>
+#include <cstdio>
+#include <deque>
+#include <new>
+#include <vector>
+
+#include "fem_internal.h"
+
+namespace {
+
+fem_status sfail(fem_ctx *ctx, fem_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+fem_status shed(fem_ctx *ctx, hipError_t e, const char *what)
+{
+    return sfail(ctx, e == hipErrorOutOfMemory ? FEM_E_NOMEM : FEM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+#define SHIP(call, what)                                  \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return shed(ctx, e_, what); \
+    } while (0)
+
+// A resident model: deep copies of the caller's Set/Map/Dat descriptors (the
+// device arrays they point to stay caller-owned), its sparsity and plans.
+struct Model {
+    fem_form form{}, src{};
+    fem_set cells{}, verts{}, nodes{};
+    fem_map cv{}, cn{};
+    fem_dat X{}, kappa{}, f{};
+    fem_args args{}, args_f{};
+    fem_sparsity sp{};
+    fem_plan *mplan = nullptr, *vplan = nullptr;
+    int64_t resident = 0;
+    int64_t nnz = 0, nrows = 0, ncells = 0;
+};
+
+struct Request {
+    int32_t model = 0;
+    int op = 0;
+    const double *x = nullptr;
+    double t_arrival = 0, t_admit = -1, t_done = -1;
+    int state = 0;        // 0 queued, 1 running, 2 done, 3 released
+    int slot = -1;
+    double *values = nullptr, *vec = nullptr;
+    int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct fem_server {
+    fem_ctx *ctx = nullptr;
+    hipStream_t home = nullptr;          // the context's stream at creation
+    int64_t budget = 0, in_use = 0, resident = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<int64_t> slot_req;        // request running on each slot, -1 if free
+    std::vector<Model *> models;
+    std::vector<Request> reqs;
+    std::deque<int64_t> queue;
+};
+
+static int64_t req_bytes(const Model &m, int op)
+{
+    return op == FEM_REQ_ASSEMBLE ? 8 * (m.nnz + m.nrows) : 8 * m.nrows;
+}
+
+extern "C" {
+
+fem_status fem_server_create(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fem_server **out)
+{
+    if (!ctx) return FEM_E_ARG;
+    if (!out || slots < 1 || slots > 64 || hbm_budget <= 0)
+        return sfail(ctx, FEM_E_ARG, "server_create: slots must be 1..64 and the budget positive");
+    fem_server *s = new (std::nothrow) fem_server;
+    if (!s) return sfail(ctx, FEM_E_NOMEM, "server_create: host allocation");
+    s->ctx = ctx;
+    s->home = ctx->stream;
+    s->budget = hbm_budget;
+    for (int i = 0; i < slots; ++i) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            fem_server_destroy(s);
+            return shed(ctx, e, "server_create: stream");
+        }
+        s->streams.push_back(st);
+        s->events.push_back(ev);
+        s->slot_req.push_back(-1);
+    }
+    *out = s;
+    return FEM_OK;
+}
+
+void fem_server_destroy(fem_server *s)
+{
+    if (!s) return;
+    for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+    for (Request &r : s->reqs) {
+        if (r.values) (void)hipFree(r.values);
+        if (r.vec) (void)hipFree(r.vec);
+    }
+    for (Model *m : s->models) {
+        fem_plan_destroy(m->mplan);
+        fem_plan_destroy(m->vplan);
+        if (m->sp.row_ptr) (void)hipFree(m->sp.row_ptr);
+        if (m->sp.col_idx) (void)hipFree(m->sp.col_idx);
+        delete m;
+    }
+    for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    if (s->ctx) s->ctx->stream = s->home;
+    delete s;
+}
+
+fem_status fem_server_add_model(fem_server *s, const fem_form *form, const fem_args *args, int32_t *model_id,
+                                int64_t *resident_bytes)
+{
+    if (!s) return FEM_E_ARG;
+    fem_ctx *ctx = s->ctx;
+    if (!form || !args || !model_id) return sfail(ctx, FEM_E_ARG, "add_model: NULL argument");
+    if (form->kind != FEM_HELMHOLTZ || form->prec != FEM_FP64 || form->dim != 1)
+        return sfail(ctx, FEM_E_UNSUPPORTED, "add_model: the server runs the FP64 Helmholtz form");
+    if (args->ncoeff < 2 || !args->coeff[0] || !args->coeff[1] || !args->cells || !args->cell_vertex ||
+        !args->cell_node || !args->coords)
+        return sfail(ctx, FEM_E_ARG, "add_model: args need cells, Maps, coords, coeff[0] = kappa, coeff[1] = f");
+    Model *m = new (std::nothrow) Model;
+    if (!m) return sfail(ctx, FEM_E_NOMEM, "add_model: host allocation");
+    m->form = *form;
+    m->src = *form;
+    m->src.kind = FEM_SOURCE;
+    m->cells = *args->cells;
+    m->verts = *args->cell_vertex->to;
+    m->nodes = *args->cell_node->to;
+    m->cv = *args->cell_vertex;
+    m->cv.from = &m->cells; m->cv.to = &m->verts;
+    m->cn = *args->cell_node;
+    m->cn.from = &m->cells; m->cn.to = &m->nodes;
+    m->X = *args->coords; m->X.set = &m->verts;
+    m->kappa = *args->coeff[0]; m->kappa.set = &m->verts;
+    m->f = *args->coeff[1]; m->f.set = &m->verts;
+    m->args.cells = &m->cells; m->args.cell_vertex = &m->cv; m->args.coords = &m->X; m->args.cell_node = &m->cn;
+    m->args.coeff[0] = &m->kappa; m->args.ncoeff = 1;
+    m->args_f = m->args;
+    m->args_f.coeff[0] = &m->f;
+    m->ncells = m->cells.size;
+    m->nrows = m->nodes.size;
+    ctx->stream = s->home;
+    auto bail = [&](fem_status st) {
+        fem_plan_destroy(m->mplan);
+        fem_plan_destroy(m->vplan);
+        if (m->sp.row_ptr) (void)hipFree(m->sp.row_ptr);
+        if (m->sp.col_idx) (void)hipFree(m->sp.col_idx);
+        delete m;
+        return st;
+    };
+    hipError_t e = hipMalloc(&m->sp.row_ptr, sizeof(int64_t) * (m->nrows + 1));
+    if (e != hipSuccess) return bail(shed(ctx, e, "add_model: alloc"));
+    fem_status st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp);
+    if (st != FEM_OK) return bail(st);
+    e = hipMalloc(&m->sp.col_idx, sizeof(int32_t) * (m->sp.nnz ? m->sp.nnz : 1));
+    if (e != hipSuccess) return bail(shed(ctx, e, "add_model: alloc"));
+    if ((st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp)) != FEM_OK) return bail(st);
+    if ((st = fem_plan_create(ctx, &m->form, &m->args, &m->sp, &m->mplan)) != FEM_OK) return bail(st);
+    if ((st = fem_plan_create(ctx, &m->form, &m->args, nullptr, &m->vplan)) != FEM_OK) return bail(st);
+    m->nnz = m->sp.nnz;
+    m->resident = 12 * m->nnz + 8 * (m->nrows + 1) + (int64_t)m->mplan->bytes + (int64_t)m->vplan->bytes;
+    if (s->resident + m->resident > s->budget)
+        return bail(sfail(ctx, FEM_E_NOMEM, "add_model: resident data exceeds the HBM budget"));
+    s->resident += m->resident;
+    *model_id = (int32_t)s->models.size();
+    s->models.push_back(m);
+    if (resident_bytes) *resident_bytes = m->resident;
+    return FEM_OK;
+}
+
+fem_status fem_server_submit(fem_server *s, int32_t model, int32_t op, const double *x, double arrival_time,
+                             int64_t *req_id)
+{
+    if (!s) return FEM_E_ARG;
+    fem_ctx *ctx = s->ctx;
+    if (model < 0 || model >= (int32_t)s->models.size()) return sfail(ctx, FEM_E_ARG, "submit: unknown model");
+    if (op != FEM_REQ_ASSEMBLE && op != FEM_REQ_ACTION) return sfail(ctx, FEM_E_ARG, "submit: unknown operation");
+    if (op == FEM_REQ_ACTION && !x && s->models[model]->nrows > 0) return sfail(ctx, FEM_E_ARG, "submit: action needs x");
+    const int64_t bytes = req_bytes(*s->models[model], op);
+    if (s->resident + bytes > s->budget)
+        return sfail(ctx, FEM_E_NOMEM, "submit: the request's outputs can never fit the HBM budget");
+    Request r;
+    r.model = model; r.op = op; r.x = x; r.t_arrival = arrival_time; r.bytes = bytes;
+    s->reqs.push_back(r);
+    s->queue.push_back((int64_t)s->reqs.size() - 1);
+    if (req_id) *req_id = (int64_t)s->reqs.size() - 1;
+    return FEM_OK;
+}
+
+fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_t *running, int32_t *queued)
+{
+    if (!s) return FEM_E_ARG;
+    fem_ctx *ctx = s->ctx;
+    int32_t done = 0;
+    // retire
+    for (size_t k = 0; k < s->streams.size(); ++k) {
+        const int64_t q = s->slot_req[k];
+        if (q < 0) continue;
+        const hipError_t e = hipEventQuery(s->events[k]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return shed(ctx, e, "poll: request failed on the device");
+        Request &r = s->reqs[q];
+        r.state = 2;
+        r.t_done = now;
+        s->slot_req[k] = -1;
+        ++done;
+    }
+    // admit the queue head while a slot is free and its outputs fit
+    while (!s->queue.empty()) {
+        Request &r = s->reqs[s->queue.front()];
+        int slot = -1;
+        for (size_t k = 0; k < s->streams.size(); ++k)
+            if (s->slot_req[k] < 0) { slot = (int)k; break; }
+        if (slot < 0 || s->resident + s->in_use + r.bytes > s->budget) break;
+        const Model &m = *s->models[r.model];
+        hipStream_t st = s->streams[slot];
+        if (r.op == FEM_REQ_ASSEMBLE) {
+            SHIP(hipMallocAsync((void **)&r.values, 8 * (m.nnz ? m.nnz : 1), st), "poll: alloc");
+            SHIP(hipMallocAsync((void **)&r.vec, 8 * (m.nrows ? m.nrows : 1), st), "poll: alloc");
+        } else {
+            SHIP(hipMallocAsync((void **)&r.vec, 8 * (m.nrows ? m.nrows : 1), st), "poll: alloc");
+        }
+        ctx->stream = st;
+        fem_status fs;
+        if (r.op == FEM_REQ_ASSEMBLE) {
+            fem_mat A{&m.sp, r.values};
+            fem_dat b{&m.nodes, 1, r.vec};
+            fs = fem_par_loop_assemble_mat(ctx, m.mplan, &m.form, &m.args, &A, FEM_WRITE);
+            if (fs == FEM_OK) fs = fem_par_loop_assemble_vec(ctx, m.vplan, &m.src, &m.args_f, &b, FEM_WRITE);
+        } else {
+            fem_dat xd{&m.nodes, 1, const_cast<double *>(r.x)};
+            fem_dat yd{&m.nodes, 1, r.vec};
+            fs = fem_apply_action(ctx, m.vplan, &m.form, &m.args, &xd, &yd, FEM_WRITE);
+        }
+        ctx->stream = s->home;
+        if (fs != FEM_OK) return fs;
+        SHIP(hipEventRecord(s->events[slot], st), "poll: event");
+        r.state = 1;
+        r.slot = slot;
+        r.t_admit = now;
+        s->in_use += r.bytes;
+        s->slot_req[slot] = s->queue.front();
+        s->queue.pop_front();
+    }
+    int32_t run = 0;
+    for (int64_t q : s->slot_req) run += q >= 0;
+    if (completed) *completed = done;
+    if (running) *running = run;
+    if (queued) *queued = (int32_t)s->queue.size();
+    return FEM_OK;
+}
+
+fem_status fem_server_result(fem_server *s, int64_t req, const double **values, const double **vec, double *t_admit,
+                             double *t_done)
+{
+    if (!s) return FEM_E_ARG;
+    if (req < 0 || req >= (int64_t)s->reqs.size()) return sfail(s->ctx, FEM_E_ARG, "result: unknown request");
+    const Request &r = s->reqs[req];
+    if (r.state != 2) return sfail(s->ctx, FEM_E_ARG, "result: request %lld is not complete", (long long)req);
+    if (values) *values = r.values;
+    if (vec) *vec = r.vec;
+    if (t_admit) *t_admit = r.t_admit;
+    if (t_done) *t_done = r.t_done;
+    return FEM_OK;
+}
+
+fem_status fem_server_release(fem_server *s, int64_t req)
+{
+    if (!s) return FEM_E_ARG;
+    fem_ctx *ctx = s->ctx;
+    if (req < 0 || req >= (int64_t)s->reqs.size()) return sfail(ctx, FEM_E_ARG, "release: unknown request");
+    Request &r = s->reqs[req];
+    if (r.state != 2) return sfail(ctx, FEM_E_ARG, "release: request %lld is not complete", (long long)req);
+    hipStream_t st = s->streams[r.slot];
+    if (r.values) SHIP(hipFreeAsync(r.values, st), "release: free");
+    if (r.vec) SHIP(hipFreeAsync(r.vec, st), "release: free");
+    r.values = r.vec = nullptr;
+    s->in_use -= r.bytes;
+    r.state = 3;
+    return FEM_OK;
+}
+
+fem_status fem_server_model_info(const fem_server *s, int32_t model, int64_t *cells, int64_t *nrows, int64_t *nnz,
+                                 const int64_t **row_ptr, const int32_t **col_idx)
+{
+    if (!s || model < 0 || model >= (int32_t)s->models.size()) return FEM_E_ARG;
+    const Model &m = *s->models[model];
+    if (cells) *cells = m.ncells;
+    if (nrows) *nrows = m.nrows;
+    if (nnz) *nnz = m.nnz;
+    if (row_ptr) *row_ptr = m.sp.row_ptr;
+    if (col_idx) *col_idx = m.sp.col_idx;
+    return FEM_OK;
+}
+
+}  // extern "C"

@@ -71,7 +71,10 @@ class fem_args(C.Structure):
 EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_error", "fem_sync",
            "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
-           "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity"]
+           "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
+           "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
+           "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info"]
+FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
 
@@ -105,8 +108,19 @@ def lib():
                                                     C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
         L.fem_expand_sparsity.argtypes = [P, C.POINTER(fem_sparsity), C.c_int32, C.POINTER(fem_sparsity)]
+        I64p = C.POINTER(C.c_int64)
+        L.fem_server_create.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(P)]
+        L.fem_server_destroy.argtypes = [P]; L.fem_server_destroy.restype = None
+        L.fem_server_add_model.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(C.c_int32), I64p]
+        L.fem_server_submit.argtypes = [P, C.c_int32, C.c_int32, P, C.c_double, I64p]
+        L.fem_server_poll.argtypes = [P, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
+        L.fem_server_result.argtypes = [P, C.c_int64, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+        L.fem_server_release.argtypes = [P, C.c_int64]
+        L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
-            if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error"):
+            if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error", "fem_server_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -299,3 +313,73 @@ def fem_renumber(ctx: Context, frm: fem_form, args: Args):
 
 def fem_sync(ctx: Context):
     ctx.check(lib().fem_sync(ctx.h))
+
+
+class Server:
+    """Request server over resident models (fem_server_*): argument
+    marshalling only.  Models keep references to their device tensors."""
+
+    def __init__(self, ctx: Context, slots: int = 8, hbm_budget: int = 64 << 30):
+        self.ctx = ctx
+        self.h = C.c_void_p()
+        ctx.check(lib().fem_server_create(ctx.h, slots, hbm_budget, C.byref(self.h)))
+        self.keep = []
+
+    def add_model(self, frm: fem_form, args: Args) -> tuple[int, int]:
+        mid, res = C.c_int32(), C.c_int64()
+        self.ctx.check(lib().fem_server_add_model(self.h, C.byref(frm), C.byref(args.c), C.byref(mid), C.byref(res)))
+        self.keep.append(args)
+        return mid.value, res.value
+
+    def model_info(self, mid: int):
+        c, r, z = C.c_int64(), C.c_int64(), C.c_int64()
+        rp, ci = C.c_void_p(), C.c_void_p()
+        self.ctx.check(lib().fem_server_model_info(self.h, mid, C.byref(c), C.byref(r), C.byref(z), C.byref(rp),
+                                                   C.byref(ci)))
+        return {"cells": c.value, "nrows": r.value, "nnz": z.value, "row_ptr": rp.value, "col_idx": ci.value}
+
+    def submit(self, mid: int, op: int, x=None, arrival: float = 0.0) -> int:
+        rid = C.c_int64()
+        self.ctx.check(lib().fem_server_submit(self.h, mid, op, _ptr(x) if x is not None else None, arrival,
+                                               C.byref(rid)))
+        return rid.value
+
+    def poll(self, now: float):
+        d, r, q = C.c_int32(), C.c_int32(), C.c_int32()
+        self.ctx.check(lib().fem_server_poll(self.h, now, C.byref(d), C.byref(r), C.byref(q)))
+        return d.value, r.value, q.value
+
+    def result(self, rid: int):
+        """(values device pointer or None, vector device pointer, t_admit, t_done)."""
+        v, b = C.c_void_p(), C.c_void_p()
+        ta, td = C.c_double(), C.c_double()
+        self.ctx.check(lib().fem_server_result(self.h, rid, C.byref(v), C.byref(b), C.byref(ta), C.byref(td)))
+        return v.value, b.value, ta.value, td.value
+
+    def release(self, rid: int):
+        self.ctx.check(lib().fem_server_release(self.h, rid))
+
+    def close(self):
+        if self.h:
+            lib().fem_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_copy(ptr: int, n: int, dtype=None):
+    """Copy n float64 values at a device address into a new torch tensor (for
+    reading server outputs); a plain device-to-device copy."""
+    import torch
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    if n:
+        hip = C.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        rc = hip.hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), 8 * n, 3)
+        if rc != 0:
+            raise FemError(FEM_E_DEVICE, f"hipMemcpy failed ({rc})")
+    return out

@@ -1,0 +1,174 @@
+"""Request server: resident models, admission by slots and HBM budget,
+overlapping requests; every result bitwise the same alone and in a mix, and
+equal to the oracle on small meshes."""
+import time
+
+import numpy as np
+import pytest
+
+import fem_inputs as fi
+import oracle
+from fem_case import check_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _model(kind, n, degree, seed):
+    st = fi.spawn_streams(seed)
+    m = fi.unit_square(n) if kind == "square" else fi.unit_cube(n)
+    m = fi.jitter_interior(m, 0.2, st["mesh"])
+    cn, N = fi.node_map(m, degree)
+    kappa = fi.field(st["kappa"], m.nverts, 0.5, 1.5)
+    f = fi.field(st["f"], m.nverts, 0.5, 1.5)
+    x = fi.field(st["x"], N, 0.5, 1.5)
+    return dict(dim=m.dim, degree=degree, cells=m.cells, coords=m.coords, cn=np.ascontiguousarray(cn, np.int32),
+                N=N, kappa=kappa, f=f, x=x)
+
+
+SPECS = [("square", 16, 1), ("square", 16, 2), ("square", 8, 3), ("cube", 3, 1), ("cube", 3, 2), ("cube", 2, 3)]
+
+
+def _server(slots, budget, specs=SPECS):
+    import torch
+    from paper_1501_01809_amd import fem as F
+    ctx = F.Context(0)
+    srv = F.Server(ctx, slots, budget)
+    models = []
+    for i, (kind, n, k) in enumerate(specs):
+        p = _model(kind, n, k, 900 + i)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        p["g"] = dict(cv=t(p["cells"]), X=t(p["coords"]), cn=t(p["cn"]), kappa=t(p["kappa"]), f=t(p["f"]),
+                      x=t(p["x"]))
+        g = p["g"]
+        args = F.Args(g["cv"], g["X"], g["cn"], p["N"], [g["kappa"], g["f"]])
+        mid, res = srv.add_model(F.form("helmholtz", p["dim"], k), args)
+        p["id"], p["resident"] = mid, res
+        p["info"] = srv.model_info(mid)
+        models.append(p)
+    return F, ctx, srv, models
+
+
+def _drain(srv, F, rids, models, ops, release=True):
+    """Poll until every request is done; return its outputs as numpy arrays."""
+    out = {}
+    pending = set(rids)
+    t0 = time.perf_counter()
+    while pending:
+        srv.poll(time.perf_counter() - t0)
+        for r in list(pending):
+            try:
+                v, b, ta, td = srv.result(r)
+            except F.FemError:
+                continue
+            m, op = models[r], ops[r]
+            vec = F.device_copy(b, m["N"]).cpu().numpy()
+            vals = F.device_copy(v, m["info"]["nnz"]).cpu().numpy() if op == F.FEM_REQ_ASSEMBLE else None
+            out[r] = (vals, vec, ta, td)
+            if release:
+                srv.release(r)
+            pending.discard(r)
+        assert time.perf_counter() - t0 < 60, "requests did not complete"
+    return out
+
+
+def _workload(F, models, reps=3):
+    seq = []
+    for rep in range(reps):
+        for p in models:
+            seq.append((p, F.FEM_REQ_ASSEMBLE))
+            seq.append((p, F.FEM_REQ_ACTION))
+    return seq
+
+
+def test_alone_equals_mix_and_oracle():
+    F, ctx, srv1, models = _server(1, 8 << 30)
+    seq = _workload(F, models)
+    alone = []
+    for p, op in seq:                                     # one at a time, one slot
+        rid = srv1.submit(p["id"], op, p["g"]["x"] if op == F.FEM_REQ_ACTION else None)
+        res = _drain(srv1, F, [rid], {rid: p}, {rid: op})
+        alone.append(res[rid])
+    # the same requests, all submitted at once to an 8-slot server
+    F2, ctx2, srv8, models8 = _server(8, 8 << 30)
+    rids, mm, oo = [], {}, {}
+    for p, op in seq:
+        q = models8[p["id"]]
+        r = srv8.submit(q["id"], op, q["g"]["x"] if op == F.FEM_REQ_ACTION else None)
+        rids.append(r); mm[r] = q; oo[r] = op
+    mix = _drain(srv8, F2, rids, mm, oo)
+    for (p, op), a, r in zip(seq, alone, rids):
+        b = mix[r]
+        assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
+        if op == F.FEM_REQ_ASSEMBLE:
+            assert np.array_equal(a[0].view(np.uint64), b[0].view(np.uint64))
+    # every result against the oracle (first repetition)
+    for (p, op), a in zip(seq[:2 * len(models)], alone):
+        if op == F.FEM_REQ_ASSEMBLE:
+            rp, ci = oracle.sparsity(p["cn"], p["N"])
+            ref, absv = oracle.assemble_mat(p["dim"], p["degree"], p["cells"], p["coords"], p["cn"], p["kappa"], rp, ci)
+            check_close(a[0], ref, absv, f"server mat {p['dim']}D P{p['degree']}")
+            b, ab = oracle.assemble_vec(p["dim"], p["degree"], p["cells"], p["coords"], p["cn"], p["f"], p["N"])
+            check_close(a[1], b, ab, "server rhs")
+        else:
+            y, ay = oracle.apply_action(p["dim"], p["degree"], p["cells"], p["coords"], p["cn"], p["kappa"], p["x"],
+                                        p["N"])
+            check_close(a[1], y, ay, "server action")
+    srv1.close(); srv8.close()
+
+
+def test_admission_respects_the_budget_and_slots():
+    F, ctx, srv, models = _server(4, 1 << 30, SPECS[:2])
+    resident = sum(p["resident"] for p in models)
+    big = models[1]
+    req = 8 * (big["info"]["nnz"] + big["N"])
+    srv.close()
+    # a budget that holds the resident models and one assembly's outputs
+    F, ctx, srv, models = _server(4, resident + req + req // 2, SPECS[:2])
+    big = models[1]
+    rids = [srv.submit(big["id"], F.FEM_REQ_ASSEMBLE) for _ in range(6)]
+    t0 = time.perf_counter()
+    seen_running = 0
+    done = set()
+    while len(done) < len(rids):
+        _, running, queued = srv.poll(time.perf_counter() - t0)
+        seen_running = max(seen_running, running)
+        for r in rids:
+            if r in done:
+                continue
+            try:
+                srv.result(r)
+            except F.FemError:
+                continue
+            srv.release(r)
+            done.add(r)
+        assert time.perf_counter() - t0 < 60
+    assert seen_running == 1          # memory, not slots, limited admission
+    srv.close()
+    with pytest.raises(F.FemError) as e:              # resident models beyond the budget
+        _server(2, resident // 2, SPECS[:2])
+    assert e.value.status == F.FEM_E_NOMEM
+    F, ctx, tiny, m2 = _server(2, resident + 64, SPECS[:2])
+    with pytest.raises(F.FemError) as e:              # outputs that can never fit
+        tiny.submit(m2[1]["id"], F.FEM_REQ_ASSEMBLE)
+    assert e.value.status == F.FEM_E_NOMEM
+    tiny.close()
+
+
+def test_server_rejections():
+    F, ctx, srv, models = _server(2, 4 << 30, SPECS[:1])
+    p = models[0]
+    with pytest.raises(F.FemError) as e:
+        srv.submit(5, F.FEM_REQ_ASSEMBLE)
+    assert e.value.status == F.FEM_E_ARG
+    with pytest.raises(F.FemError) as e:
+        srv.submit(p["id"], F.FEM_REQ_ACTION, None)
+    assert e.value.status == F.FEM_E_ARG
+    rid = srv.submit(p["id"], F.FEM_REQ_ASSEMBLE)
+    with pytest.raises(F.FemError) as e:              # not admitted yet: no poll has run
+        srv.result(rid)
+    assert e.value.status == F.FEM_E_ARG
+    _drain(srv, F, [rid], {rid: p}, {rid: F.FEM_REQ_ASSEMBLE})
+    with pytest.raises(F.FemError) as e:              # released already
+        srv.release(rid)
+    assert e.value.status == F.FEM_E_ARG
+    srv.close()
