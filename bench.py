@@ -273,6 +273,134 @@ def bench_precision(ctx, steps: int, warmup: int, seed: int, n: int = 48):
     return out
 
 
+def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: int = 8):
+    """The serving workload: a stream of `nreq` requests with Poisson arrivals
+    at rate load / s, s the mean isolated service time of the mix.  Each
+    request is an assembly (CSR matrix + right-hand side) or a matrix-free
+    action, drawn uniformly, on a resident model drawn uniformly by mesh kind
+    (unit-square triangles, n in 16..512; Kuhn cubes, n in 8..64), size and
+    Lagrange degree 1..3; jittered meshes, fields U[0.5, 1.5].  The same
+    arrival sequence is served with `slots` slots and with one slot (no
+    overlap).  Latency = completion seen by the poll loop minus arrival."""
+    import torch
+    import fem_inputs as fi
+    from paper_1501_01809_amd import fem as F
+    dev = torch.device("cuda:0")
+    kinds = {"square": [16, 32, 64, 128, 256, 512], "cube": [8, 16, 32, 64]}
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rng = np.random.default_rng(seed + 5)
+    specs, keep = [], []
+    t0 = time.perf_counter()
+    for kind, sizes in kinds.items():
+        for n in sizes:
+            st = fi.spawn_streams(seed + n)
+            m = fi.jitter_interior(fi.unit_square(n) if kind == "square" else fi.unit_cube(n), 0.2, st["mesh"])
+            for k in (1, 2, 3):
+                cn, N = fi.node_map(m, k)
+                g = dict(cv=t(m.cells), X=t(m.coords), cn=t(cn.astype(np.int32)),
+                         kappa=t(fi.field(st["kappa"], m.nverts, 0.5, 1.5)),
+                         f=t(fi.field(st["f"], m.nverts, 0.5, 1.5)), x=t(fi.field(st["x"], N, 0.5, 1.5)))
+                specs.append(dict(kind=kind, n=n, degree=k, dim=m.dim, cells=m.ncells, N=N, g=g))
+    build_ms = (time.perf_counter() - t0) * 1e3
+
+    def make_server(ns):
+        srv = F.Server(ctx, ns, 96 << 30)
+        for sp_ in specs:
+            g = sp_["g"]
+            mid, res = srv.add_model(F.form("helmholtz", sp_["dim"], sp_["degree"]),
+                                     F.Args(g["cv"], g["X"], g["cn"], sp_["N"], [g["kappa"], g["f"]]))
+            sp_["id"], sp_["resident"] = mid, res
+        return srv
+
+    log(f"serving: inputs of {len(specs)} models built ({build_ms / 1e3:.1f} s)")
+    t0 = time.perf_counter()
+    srv = make_server(slots)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    resident = sum(sp_["resident"] for sp_ in specs)
+
+    def serve_one(srv_, sp_, op):
+        rid = srv_.submit(sp_["id"], op, sp_["g"]["x"] if op == F.FEM_REQ_ACTION else None, 0.0)
+        c0 = time.perf_counter()
+        while True:
+            c, _, _ = srv_.poll(time.perf_counter() - c0)
+            if c and rid in srv_.take_completed():
+                break
+        _, _, _, td = srv_.result(rid)
+        srv_.release(rid)
+        return td
+
+    # service time of every (model, op) alone with warm caches (best of two
+    # after a warm-up), for reference
+    iso = {}
+    for sp_ in specs:
+        for op in (F.FEM_REQ_ASSEMBLE, F.FEM_REQ_ACTION):
+            serve_one(srv, sp_, op)
+            iso[(sp_["id"], op)] = min(serve_one(srv, sp_, op), serve_one(srv, sp_, op))
+    # the request mix: kind uniform, then size, degree and op uniform
+    by_kind = {kd: [sp_ for sp_ in specs if sp_["kind"] == kd] for kd in kinds}
+
+    def draw():
+        kd = list(kinds)[rng.integers(2)]
+        return by_kind[kd][rng.integers(len(by_kind[kd]))], int(rng.integers(2))
+
+    # mean isolated service time s of the mix: a sample of 512 requests, each
+    # served alone (submitted after the previous one completed), in mix order,
+    # so that caches hold what a stream of mixed requests leaves in them
+    sample = [draw() for _ in range(512)]
+    sbar = float(np.mean([serve_one(srv, sp_, op) for sp_, op in sample]))
+    rate = load / sbar
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    for i in range(nreq):
+        sp_, op = draw()
+        reqs.append((sp_, op, float(arrivals[i])))
+
+    def run(srv_):
+        lat = np.zeros(nreq); svc = np.zeros(nreq); cells = 0
+        ids = {}
+        nxt = 0; done = 0
+        c0 = time.perf_counter()
+        while done < nreq:
+            now = time.perf_counter() - c0
+            while nxt < nreq and reqs[nxt][2] <= now:
+                sp_, op, ta = reqs[nxt]
+                rid = srv_.submit(sp_["id"], op, sp_["g"]["x"] if op == F.FEM_REQ_ACTION else None, ta)
+                ids[rid] = nxt
+                nxt += 1
+            c, _, _ = srv_.poll(now)
+            if c:
+                for rid in srv_.take_completed():
+                    _, _, ta, td = srv_.result(rid)
+                    i = ids.pop(rid)
+                    lat[i] = td - reqs[i][2]
+                    svc[i] = td - ta
+                    cells += reqs[i][0]["cells"]
+                    srv_.release(rid)
+                    done += 1
+        span = time.perf_counter() - c0
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "makespan_s": span, "cells_per_s": cells / span,
+                "admit_to_done_mean_ms": float(svc.mean() * 1e3)}
+
+    out = {"workload": f"{nreq} requests, Poisson arrivals at {load} / mean isolated service time; assembly "
+                       f"(CSR + RHS) or action, unit-square triangle meshes n=16..512 and Kuhn cubes n=8..64, "
+                       f"P1-P3, fields U[0.5,1.5]; {len(specs)} resident models",
+           "models": len(specs), "resident_bytes": resident, "inputs_ms": build_ms, "setup_ms": setup_ms,
+           "mean_isolated_service_ms": sbar * 1e3, "arrival_rate_per_s": rate, "slots": slots,
+           "isolated_ms": {f"{sp_['kind']}{sp_['n']}p{sp_['degree']}": [round(iso[(sp_['id'], 0)] * 1e3, 3),
+                                                                       round(iso[(sp_['id'], 1)] * 1e3, 3)]
+                           for sp_ in specs}}
+    log(f"serving: {len(specs)} models resident ({resident / 1e9:.1f} GB), setup {setup_ms / 1e3:.1f} s, "
+        f"mean isolated service {sbar * 1e3:.3f} ms; {slots} slots")
+    out["batched"] = run(srv)
+    log(f"serving: {slots} slots p50 {out['batched']['p50_ms']:.2f} ms p99 {out['batched']['p99_ms']:.2f} ms")
+    srv.set_slots(1)
+    out["one_slot"] = run(srv)
+    log(f"serving: 1 slot p50 {out['one_slot']['p50_ms']:.2f} ms p99 {out['one_slot']['p99_ms']:.2f} ms")
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +418,9 @@ def main():
                     help="skip the differentiation workload (residual and adjoint, 512x512x2 triangles)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the precision workload (vector P2 elasticity, 48^3x6, four precisions)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving workload (4096 requests on 30 resident models)")
+    ap.add_argument("--serving-requests", type=int, default=4096)
     ap.add_argument("--ops", default="mat,vec,action",
                     help="operations run in a step (a subset is for profiling the kernels one by one; "
                          "the reported metric needs all three)")
@@ -439,6 +570,8 @@ def main():
         out["differentiation"] = bench_nl(ctx, args.steps, args.warmup, args.seed)
     if not args.no_precision:
         out["precision"] = bench_precision(ctx, args.steps, args.warmup, args.seed)
+    if not args.no_serving:
+        out["serving"] = bench_serving(ctx, args.seed, args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, args.degree, min(args.cpu_sample, C), dim)
         out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]

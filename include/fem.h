@@ -329,9 +329,12 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
  * fem_server_poll, which never blocks, retires requests whose work has
  * finished and admits the queue head while one of the `slots` is free and the
  * request's outputs fit the HBM budget (hbm_budget bytes for resident models
- * plus outputs in flight).  An admitted request's output memory is allocated
- * stream-ordered and its kernels are queued on its slot's stream, so requests
- * admitted while others run overlap with them on the device.  Its outputs
+ * plus outputs in flight).  Outputs come from an arena of the budget left
+ * after the resident models, allocated at the first admission (so models
+ * must be added before the first poll that admits a request) and carved on
+ * the host without driver calls.  An admitted request's kernels are queued
+ * on its slot's stream, so requests admitted while others run overlap with
+ * them on the device.  Its outputs
  * (device pointers from fem_server_result: CSR values in the model's
  * sparsity order and the vector, or y) stay valid until fem_server_release
  * returns their memory to the budget.  Results do not depend on the mix:
@@ -356,6 +359,12 @@ fem_status fem_server_poll(fem_server *server, double now, int32_t *completed, i
 fem_status fem_server_result(fem_server *server, int64_t request_id, const double **values,
                              const double **vec, double *t_admit, double *t_done);
 fem_status fem_server_release(fem_server *server, int64_t request_id);
+/* Hand out up to cap ids of requests completed (by earlier polls) and not yet
+ * handed out, in completion order; *n receives the count. */
+fem_status fem_server_take_completed(fem_server *server, int64_t *ids, int32_t cap, int32_t *n);
+/* Limit admission to the first `slots` slots (1..the number created); requests
+ * already running elsewhere finish normally. */
+fem_status fem_server_set_slots(fem_server *server, int32_t slots);
 /* A resident model's sizes and its sparsity (device pointers owned by the server). */
 fem_status fem_server_model_info(const fem_server *server, int32_t model, int64_t *cells, int64_t *nrows,
                                  int64_t *nnz, const int64_t **row_ptr, const int32_t **col_idx);

@@ -18,6 +18,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -70,6 +72,49 @@ struct Request {
     int slot = -1;
     double *values = nullptr, *vec = nullptr;
     int64_t bytes = 0;
+    int64_t off_values = -1, off_vec = -1;
+};
+
+// Device output arena: one allocation of the budget left after the resident
+// models, carved first-fit into 256-byte aligned ranges on the host.  Taking
+// and returning a range costs no driver call; a range is handed out again
+// only after its request was released, i.e. after its kernels finished and
+// the caller read the results.
+struct Arena {
+    char *base = nullptr;
+    int64_t size = 0;
+    std::map<int64_t, int64_t> free_;   // offset -> length, coalesced
+    static int64_t round(int64_t b) { return (b + 255) / 256 * 256; }
+    bool take(int64_t bytes, int64_t *off)
+    {
+        bytes = round(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                *off = it->first;
+                const int64_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void give(int64_t off, int64_t bytes)
+    {
+        bytes = round(bytes ? bytes : 1);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
 };
 
 }  // namespace
@@ -78,12 +123,15 @@ struct fem_server {
     fem_ctx *ctx = nullptr;
     hipStream_t home = nullptr;          // the context's stream at creation
     int64_t budget = 0, in_use = 0, resident = 0;
+    int active = 0;                       // slots admission may use (<= streams.size())
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int64_t> slot_req;        // request running on each slot, -1 if free
     std::vector<Model *> models;
     std::vector<Request> reqs;
     std::deque<int64_t> queue;
+    std::deque<int64_t> finished;         // completed, not yet handed out by take_completed
+    Arena arena;                          // allocated at the first admission
 };
 
 static int64_t req_bytes(const Model &m, int op)
@@ -103,6 +151,7 @@ fem_status fem_server_create(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fe
     s->ctx = ctx;
     s->home = ctx->stream;
     s->budget = hbm_budget;
+    s->active = slots;
     for (int i = 0; i < slots; ++i) {
         hipStream_t st = nullptr;
         hipEvent_t ev = nullptr;
@@ -124,10 +173,7 @@ void fem_server_destroy(fem_server *s)
 {
     if (!s) return;
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-    for (Request &r : s->reqs) {
-        if (r.values) (void)hipFree(r.values);
-        if (r.vec) (void)hipFree(r.vec);
-    }
+    if (s->arena.base) (void)hipFree(s->arena.base);
     for (Model *m : s->models) {
         fem_plan_destroy(m->mplan);
         fem_plan_destroy(m->vplan);
@@ -147,6 +193,7 @@ fem_status fem_server_add_model(fem_server *s, const fem_form *form, const fem_a
     if (!s) return FEM_E_ARG;
     fem_ctx *ctx = s->ctx;
     if (!form || !args || !model_id) return sfail(ctx, FEM_E_ARG, "add_model: NULL argument");
+    if (s->arena.base) return sfail(ctx, FEM_E_ARG, "add_model: models must be added before the first admission");
     if (form->kind != FEM_HELMHOLTZ || form->prec != FEM_FP64 || form->dim != 1)
         return sfail(ctx, FEM_E_UNSUPPORTED, "add_model: the server runs the FP64 Helmholtz form");
     if (args->ncoeff < 2 || !args->coeff[0] || !args->coeff[1] || !args->cells || !args->cell_vertex ||
@@ -237,23 +284,36 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
         r.state = 2;
         r.t_done = now;
         s->slot_req[k] = -1;
+        s->finished.push_back(q);
         ++done;
+    }
+    // the output arena: everything the resident models leave of the budget
+    if (!s->arena.base && !s->queue.empty()) {
+        const int64_t size = (s->budget - s->resident) / 256 * 256;
+        SHIP(hipMalloc((void **)&s->arena.base, size), "poll: output arena");
+        s->arena.size = size;
+        s->arena.free_[0] = size;
     }
     // admit the queue head while a slot is free and its outputs fit
     while (!s->queue.empty()) {
         Request &r = s->reqs[s->queue.front()];
         int slot = -1;
-        for (size_t k = 0; k < s->streams.size(); ++k)
-            if (s->slot_req[k] < 0) { slot = (int)k; break; }
+        for (int k = 0; k < s->active; ++k)
+            if (s->slot_req[k] < 0) { slot = k; break; }
         if (slot < 0 || s->resident + s->in_use + r.bytes > s->budget) break;
         const Model &m = *s->models[r.model];
         hipStream_t st = s->streams[slot];
-        if (r.op == FEM_REQ_ASSEMBLE) {
-            SHIP(hipMallocAsync((void **)&r.values, 8 * (m.nnz ? m.nnz : 1), st), "poll: alloc");
-            SHIP(hipMallocAsync((void **)&r.vec, 8 * (m.nrows ? m.nrows : 1), st), "poll: alloc");
-        } else {
-            SHIP(hipMallocAsync((void **)&r.vec, 8 * (m.nrows ? m.nrows : 1), st), "poll: alloc");
+        // outputs from the arena (fragmentation may refuse what the budget
+        // allows: then wait for releases)
+        int64_t ov = -1, ob = -1;
+        if (!s->arena.take(8 * m.nrows, &ob)) break;
+        if (r.op == FEM_REQ_ASSEMBLE && !s->arena.take(8 * m.nnz, &ov)) {
+            s->arena.give(ob, 8 * m.nrows);
+            break;
         }
+        r.off_vec = ob; r.off_values = ov;
+        r.vec = reinterpret_cast<double *>(s->arena.base + ob);
+        r.values = ov >= 0 ? reinterpret_cast<double *>(s->arena.base + ov) : nullptr;
         ctx->stream = st;
         fem_status fs;
         if (r.op == FEM_REQ_ASSEMBLE) {
@@ -305,12 +365,34 @@ fem_status fem_server_release(fem_server *s, int64_t req)
     if (req < 0 || req >= (int64_t)s->reqs.size()) return sfail(ctx, FEM_E_ARG, "release: unknown request");
     Request &r = s->reqs[req];
     if (r.state != 2) return sfail(ctx, FEM_E_ARG, "release: request %lld is not complete", (long long)req);
-    hipStream_t st = s->streams[r.slot];
-    if (r.values) SHIP(hipFreeAsync(r.values, st), "release: free");
-    if (r.vec) SHIP(hipFreeAsync(r.vec, st), "release: free");
+    const Model &m = *s->models[r.model];
+    if (r.off_values >= 0) s->arena.give(r.off_values, 8 * m.nnz);
+    if (r.off_vec >= 0) s->arena.give(r.off_vec, 8 * m.nrows);
     r.values = r.vec = nullptr;
+    r.off_values = r.off_vec = -1;
     s->in_use -= r.bytes;
     r.state = 3;
+    return FEM_OK;
+}
+
+fem_status fem_server_take_completed(fem_server *s, int64_t *ids, int32_t cap, int32_t *n)
+{
+    if (!s || !n || (cap > 0 && !ids)) return FEM_E_ARG;
+    int32_t k = 0;
+    while (k < cap && !s->finished.empty()) {
+        ids[k++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    *n = k;
+    return FEM_OK;
+}
+
+fem_status fem_server_set_slots(fem_server *s, int32_t slots)
+{
+    if (!s) return FEM_E_ARG;
+    if (slots < 1 || slots > (int32_t)s->streams.size())
+        return sfail(s->ctx, FEM_E_ARG, "set_slots: 1..%d", (int)s->streams.size());
+    s->active = slots;   // running requests on higher slots finish normally
     return FEM_OK;
 }
 

@@ -73,7 +73,8 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
-           "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info"]
+           "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
+           "fem_server_set_slots", "fem_server_take_completed"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
@@ -118,6 +119,8 @@ def lib():
         L.fem_server_result.argtypes = [P, C.c_int64, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.fem_server_release.argtypes = [P, C.c_int64]
+        L.fem_server_set_slots.argtypes = [P, C.c_int32]
+        L.fem_server_take_completed.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
             if name not in ("fem_ctx_destroy", "fem_plan_destroy", "fem_last_error", "fem_server_destroy"):
@@ -358,6 +361,15 @@ class Server:
 
     def release(self, rid: int):
         self.ctx.check(lib().fem_server_release(self.h, rid))
+
+    def take_completed(self, cap: int = 256) -> list[int]:
+        buf = np.zeros(cap, dtype=np.int64)
+        n = C.c_int32()
+        self.ctx.check(lib().fem_server_take_completed(self.h, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
+        return buf[:n.value].tolist()
+
+    def set_slots(self, slots: int):
+        self.ctx.check(lib().fem_server_set_slots(self.h, slots))
 
     def close(self):
         if self.h:
