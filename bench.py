@@ -392,11 +392,10 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
                            for sp_ in specs}}
     log(f"serving: {len(specs)} models resident ({resident / 1e9:.1f} GB), setup {setup_ms / 1e3:.1f} s, "
         f"mean isolated service {sbar * 1e3:.3f} ms; {slots} slots")
-    out["batched"] = run(srv)
-    log(f"serving: {slots} slots p50 {out['batched']['p50_ms']:.2f} ms p99 {out['batched']['p99_ms']:.2f} ms")
-    srv.set_slots(1)
-    out["one_slot"] = run(srv)
-    log(f"serving: 1 slot p50 {out['one_slot']['p50_ms']:.2f} ms p99 {out['one_slot']['p99_ms']:.2f} ms")
+    for name, ns, share in (("batched", slots, True), ("batched_full_grid", slots, False), ("one_slot", 1, False)):
+        srv.configure(ns, share)
+        out[name] = run(srv)
+        log(f"serving: {name} ({ns} slots) p50 {out[name]['p50_ms']:.2f} ms p99 {out[name]['p99_ms']:.2f} ms")
     srv.close()
     return out
 

@@ -362,9 +362,12 @@ fem_status fem_server_release(fem_server *server, int64_t request_id);
 /* Hand out up to cap ids of requests completed (by earlier polls) and not yet
  * handed out, in completion order; *n receives the count. */
 fem_status fem_server_take_completed(fem_server *server, int64_t *ids, int32_t cap, int32_t *n);
-/* Limit admission to the first `slots` slots (1..the number created); requests
- * already running elsewhere finish normally. */
-fem_status fem_server_set_slots(fem_server *server, int32_t slots);
+/* Admission policy: use only the first `slots` slots (1..the number created;
+ * requests already running elsewhere finish normally); with share_cus != 0
+ * (the default) a CSR assembly admitted while other requests run or wait
+ * launches its persistent Mat kernel on half the compute units, so that it
+ * does not shut the others out for its whole duration. */
+fem_status fem_server_configure(fem_server *server, int32_t slots, int32_t share_cus);
 /* A resident model's sizes and its sparsity (device pointers owned by the server). */
 fem_status fem_server_model_info(const fem_server *server, int32_t model, int64_t *cells, int64_t *nrows,
                                  int64_t *nnz, const int64_t **row_ptr, const int32_t **col_idx);

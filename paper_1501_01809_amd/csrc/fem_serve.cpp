@@ -124,6 +124,7 @@ struct fem_server {
     hipStream_t home = nullptr;          // the context's stream at creation
     int64_t budget = 0, in_use = 0, resident = 0;
     int active = 0;                       // slots admission may use (<= streams.size())
+    int share_cus = 1;                    // halve the Mat kernel's grid while others run
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int64_t> slot_req;        // request running on each slot, -1 if free
@@ -319,7 +320,15 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
         if (r.op == FEM_REQ_ASSEMBLE) {
             fem_mat A{&m.sp, r.values};
             fem_dat b{&m.nodes, 1, r.vec};
+            // the Mat kernel is persistent (one workgroup per CU); while other
+            // requests run or wait it takes half the CUs so that they are not
+            // shut out for its whole duration
+            bool busy = s->queue.size() > 1;
+            for (int64_t q : s->slot_req) busy |= q >= 0;
+            const int cus = ctx->num_cus;
+            if (busy && s->share_cus) ctx->num_cus = cus > 1 ? cus / 2 : 1;
             fs = fem_par_loop_assemble_mat(ctx, m.mplan, &m.form, &m.args, &A, FEM_WRITE);
+            ctx->num_cus = cus;
             if (fs == FEM_OK) fs = fem_par_loop_assemble_vec(ctx, m.vplan, &m.src, &m.args_f, &b, FEM_WRITE);
         } else {
             fem_dat xd{&m.nodes, 1, const_cast<double *>(r.x)};
@@ -387,12 +396,13 @@ fem_status fem_server_take_completed(fem_server *s, int64_t *ids, int32_t cap, i
     return FEM_OK;
 }
 
-fem_status fem_server_set_slots(fem_server *s, int32_t slots)
+fem_status fem_server_configure(fem_server *s, int32_t slots, int32_t share_cus)
 {
     if (!s) return FEM_E_ARG;
     if (slots < 1 || slots > (int32_t)s->streams.size())
-        return sfail(s->ctx, FEM_E_ARG, "set_slots: 1..%d", (int)s->streams.size());
+        return sfail(s->ctx, FEM_E_ARG, "configure: slots must be 1..%d", (int)s->streams.size());
     s->active = slots;   // running requests on higher slots finish normally
+    s->share_cus = share_cus != 0;
     return FEM_OK;
 }
 

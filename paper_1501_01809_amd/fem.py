@@ -74,7 +74,7 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
-           "fem_server_set_slots", "fem_server_take_completed"]
+           "fem_server_configure", "fem_server_take_completed"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
@@ -119,7 +119,7 @@ def lib():
         L.fem_server_result.argtypes = [P, C.c_int64, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
         L.fem_server_release.argtypes = [P, C.c_int64]
-        L.fem_server_set_slots.argtypes = [P, C.c_int32]
+        L.fem_server_configure.argtypes = [P, C.c_int32, C.c_int32]
         L.fem_server_take_completed.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
@@ -368,8 +368,8 @@ class Server:
         self.ctx.check(lib().fem_server_take_completed(self.h, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)))
         return buf[:n.value].tolist()
 
-    def set_slots(self, slots: int):
-        self.ctx.check(lib().fem_server_set_slots(self.h, slots))
+    def configure(self, slots: int, share_cus: bool = True):
+        self.ctx.check(lib().fem_server_configure(self.h, slots, int(share_cus)))
 
     def close(self):
         if self.h:
