@@ -6,7 +6,8 @@ bilinear form, the source linear form and the matrix-free action, with its own
 sparsity; and the nonlinear residual kappa grad(u).grad(v) + u^3 v - f v with
 its vector-Jacobian products (the adjoint assembly); and vector Lagrange
 linear elasticity 2 mu eps(u):eps(v) + lam div(u) div(v) on per-cell
-coordinates (the precision benchmark).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+coordinates (the precision benchmark); and per-cell contributions to Global
+reductions (cell energies x_K^T A_K x_K, integrals of f).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The product library never does.
 
 Every function here follows the paper's definition of a parallel loop over
@@ -71,6 +72,8 @@ def lib():
         L.oracle_nl_residual.restype = I
         L.oracle_nl_adjoint.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P, P, P]
         L.oracle_nl_adjoint.restype = I
+        L.oracle_cell_values.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, P, P, P, P]
+        L.oracle_cell_values.restype = I
         L.oracle_elasticity_element.argtypes = [I, I, P, P, P, P, P]
         L.oracle_elasticity_element.restype = I
         L.oracle_elasticity_mat.argtypes = [I, I, L64, P, P, P, P, P, P, P, L64, P, P]
@@ -320,3 +323,20 @@ def elasticity_rows(dim, degree, cell_vertex, xdg, cell_node, mu, lam, nrows, ro
         raise RuntimeError(f"oracle elasticity_rows failed ({tot})")
     return [(cols[ptr[s]:ptr[s + 1]].copy(), vals[ptr[s]:ptr[s + 1]].copy(),
              absv[ptr[s]:ptr[s + 1]].copy()) for s in range(rows.size)]
+
+
+def cell_values(kind, dim, degree, cell_vertex, coords, cell_node, field, x=None, form="helmholtz"):
+    """Per-cell Global contributions: kind "energy" (x_K^T A_K x_K, field =
+    kappa) or "integral" (integral of f over K, field = f).  Returns (q, q_abs,
+    sum in cell order, sum of magnitudes)."""
+    cs, cm = FORMS[form]
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    fld = _c(field, np.float64)
+    xx = _c(x, np.float64) if x is not None else None
+    C_ = cv.shape[0]
+    q = np.zeros(C_); qa = np.zeros(C_); s_ = np.zeros(1); sa = np.zeros(1)
+    rc = lib().oracle_cell_values(0 if kind == "energy" else 1, dim, degree, C_, _p(cv), _p(X), _p(cn), _p(fld),
+                                  cs, cm, None if xx is None else _p(xx), _p(q), _p(qa), _p(s_), _p(sa))
+    if rc:
+        raise RuntimeError(f"oracle cell_values failed ({rc})")
+    return q, qa, float(s_[0]), float(sa[0])

@@ -996,3 +996,46 @@ int64_t oracle_elasticity_rows(int dim, int degree, int64_t ncells, const int32_
     free(slot); free(cols); free(vals); free(abss); free(cnt); free(A); free(Aa);
     return rc ? rc : total;
 }
+
+/* ------------------------------------------------------------------ */
+/* Global reductions over cells (PyOP2 Globals: SUM, MIN, MAX)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Per-cell contributions to a Global: the cell energy of the bilinear form,
+ * q_K = x_K^T A_K x_K (kind 0; A_K the element matrix of cstiff kappa
+ * grad u.grad v + cmass u v, x a field of the P_k space), or the integral of
+ * the P1 field f over K (kind 1).  q[c] and its magnitude scale qa[c]; the
+ * totals in cell index order go to *sum and *sum_abs.
+ */
+int oracle_cell_values(int kind, int dim, int degree, int64_t ncells, const int32_t *cell_vertex,
+                       const double *coords, const int32_t *cell_node, const double *field, double cstiff,
+                       double cmass, const double *x, double *q, double *qa, double *sum, double *sum_abs)
+{
+    const int n = oracle_nloc(dim, degree);
+    if (n < 0) return -1;
+    double xv[12], fv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC], be[MAXLOC], ba[MAXLOC];
+    double s = 0.0, sa = 0.0;
+    for (int64_t c = 0; c < ncells; ++c) {
+        gather_cell(dim, c, cell_vertex, coords, field, xv, fv);
+        double t = 0.0, ta = 0.0;
+        if (kind == 0) {
+            if (oracle_element_matrix(dim, degree, xv, fv, cstiff, cmass, A, Aa)) return -1;
+            for (int i = 0; i < n; ++i) {
+                const double xi = x[cell_node[c * n + i]];
+                for (int j = 0; j < n; ++j) {
+                    const double xj = x[cell_node[c * n + j]];
+                    t += xi * A[i * n + j] * xj;
+                    ta += fabs(xi) * Aa[i * n + j] * fabs(xj);
+                }
+            }
+        } else {
+            if (oracle_element_vector(dim, degree, xv, fv, be, ba)) return -1;
+            for (int i = 0; i < n; ++i) { t += be[i]; ta += ba[i]; }
+        }
+        q[c] = t; qa[c] = ta;
+        s += t; sa += ta;
+    }
+    *sum = s; *sum_abs = sa;
+    return 0;
+}
