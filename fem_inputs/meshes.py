@@ -160,6 +160,17 @@ def flatten_cells(xdg: np.ndarray, fraction: float, rng: np.random.Generator, ra
     return np.ascontiguousarray(x), chosen
 
 
+def boundary_nodes(mesh: Mesh, cell_node: np.ndarray, degree: int) -> np.ndarray:
+    """uint8 mask over the nodes of a degree-k space on the unit square or
+    cube: 1 for nodes on the boundary (a coordinate equal to 0 or 1; jitter
+    moves interior vertices only, so boundary nodes stay exactly on it)."""
+    W = local_node_barycentrics(mesh.dim, degree) / degree
+    N = int(cell_node.max()) + 1
+    pos = np.zeros((N, mesh.dim))
+    pos[cell_node] = np.einsum("ln,cnd->cld", W, mesh.coords[mesh.cells])
+    return np.any((pos <= 1e-12) | (pos >= 1 - 1e-12), axis=1).astype(np.uint8)
+
+
 def local_node_barycentrics(dim: int, degree: int) -> np.ndarray:
     """Integer barycentric weights (rows sum to ``degree``) of the local nodes."""
     nv = dim + 1

@@ -88,10 +88,11 @@ typedef enum fem_status {
     FEM_E_DEVICE = 6        /* HIP runtime or kernel error                      */
 } fem_status;
 
-/* Access descriptors ("Access descriptors").  READ for inputs; a Mat or an
+/* Access descriptors ("Access descriptors"; SUM, MIN and MAX are the
+ * reductions of a Global, "Global arguments").  READ for inputs; a Mat or an
  * output Dat accepts WRITE (overwrite with the assembled sum) or INC (add the
  * assembled sum to the existing values). */
-typedef enum fem_access { FEM_READ = 0, FEM_WRITE = 1, FEM_INC = 2 } fem_access;
+typedef enum fem_access { FEM_READ = 0, FEM_WRITE = 1, FEM_INC = 2, FEM_SUM = 3, FEM_MIN = 4, FEM_MAX = 5 } fem_access;
 
 typedef enum fem_cell { FEM_TRIANGLE = 2, FEM_TETRAHEDRON = 3 } fem_cell;
 
@@ -145,6 +146,12 @@ typedef struct fem_mat {
     const fem_sparsity *sp;
     double *values;
 } fem_mat;
+
+/* A Global: one float64 value in device memory, visible from every cell
+ * ("Global arguments"). */
+typedef struct fem_global {
+    double *data;
+} fem_global;
 
 /* The local kernel: form kind, cell shape, Lagrange degree of the test and
  * trial space (1..3), value dimension of that space (1; 3 for
@@ -289,6 +296,39 @@ fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const f
 fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
                                          const fem_args *args, const fem_dat *lambda, fem_dat *g_u,
                                          fem_dat *g_kappa, fem_access acc);
+
+/*
+ * Global reduction over the cells ("Global arguments": globally integrated
+ * quantities such as energy).  Each cell contributes q_K:
+ *   bilinear forms (FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ): the cell energy
+ *     x_K^T A_K x_K of the field x (a Dat on the nodes), so that the SUM is
+ *     the energy x^T A x without forming A;
+ *   FEM_SOURCE: the integral of the P1 field f = coeff[0] over K (x unused,
+ *     may be NULL), so that the SUM is the integral of f.
+ * acc = FEM_SUM adds the sum of the q_K to g, FEM_MIN / FEM_MAX replace g by
+ * the minimum / maximum of g and the q_K (initialise g to 0 or +/-inf as
+ * wanted).  Plan: a Dat plan (sp == NULL), whose partial buffer the call uses,
+ * so calls on one plan must not overlap.  The combination order is fixed by
+ * cell index, so the value is bitwise reproducible.  Asynchronous; allocates
+ * nothing.
+ */
+fem_status fem_par_loop_reduce(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                               const fem_dat *x, fem_global *g, fem_access acc);
+
+/*
+ * Dirichlet boundary conditions on an assembled system, in place (the paper's
+ * Firedrake example assembles A with a DirichletBC and applies it to b).  For
+ * every row r with mask[r] != 0: row r and column r of A become zero except
+ * A[r][r] = diag, and b[r] = diag g[r].  Every other row i first lifts the
+ * boundary values, b[i] -= A[i][r] g[r] for its boundary columns r (column
+ * order), so that the modified system keeps the solution and stays
+ * symmetric.  mask: uint8 [nrows] device; values: the Mat's values in sp's
+ * order; b and g: float64 [nrows] device, g NULL for homogeneous conditions,
+ * b NULL to modify A only (then g must be NULL).  Square Mats only.
+ * Asynchronous; allocates nothing.
+ */
+fem_status fem_apply_dirichlet(fem_ctx *ctx, const fem_sparsity *sp, double *values, const uint8_t *mask,
+                               double diag, double *b, const double *g);
 
 /* Matrix-free action y (+)= A x with A the assembled bilinear form, computed
  * cell by cell without forming the CSR matrix (the paper's wave benchmark

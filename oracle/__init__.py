@@ -340,3 +340,31 @@ def cell_values(kind, dim, degree, cell_vertex, coords, cell_node, field, x=None
     if rc:
         raise RuntimeError(f"oracle cell_values failed ({rc})")
     return q, qa, float(s_[0]), float(sa[0])
+
+
+def apply_dirichlet(row_ptr, col_idx, values, b, mask, g=None, diag=1.0):
+    """Symmetric Dirichlet rows and columns of an assembled system (the
+    boundary condition applied at assembly in the paper's Firedrake example):
+    for every DOF r with mask[r], b[i] -= A[i][r] g[r] on the free rows i
+    (lifting), then row r and column r become zero except A[r][r] = diag, and
+    b[r] = diag g[r].  Plain loops over the CSR, rows in order; returns new
+    arrays (values, b) and the magnitude scale of each b entry."""
+    vals = np.array(values, dtype=np.float64, copy=True)
+    bb = np.array(b, dtype=np.float64, copy=True)
+    babs = np.abs(bb)
+    gg = np.zeros(len(bb)) if g is None else np.asarray(g, dtype=np.float64)
+    for r in range(len(row_ptr) - 1):
+        for k in range(row_ptr[r], row_ptr[r + 1]):
+            c = col_idx[k]
+            if mask[r]:
+                continue
+            if mask[c]:
+                bb[r] -= vals[k] * gg[c]
+                babs[r] += abs(vals[k] * gg[c])
+                vals[k] = 0.0
+        if mask[r]:
+            for k in range(row_ptr[r], row_ptr[r + 1]):
+                vals[k] = diag if col_idx[k] == r else 0.0
+            bb[r] = diag * gg[r]
+            babs[r] = abs(bb[r])
+    return vals, bb, babs

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfem.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip", "fem_elast.hip", "fem_serve.cpp"]
+SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip", "fem_elast.hip", "fem_serve.cpp", "fem_global.hip", "fem_bc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

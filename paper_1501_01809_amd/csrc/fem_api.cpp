@@ -142,7 +142,7 @@ void free_plan_arrays(fem_plan *p)
 {
     void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
                     p->blk_hdr, p->blk_w, p->wq, p->pstream,
-                    p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work};
+                    p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work, p->red_partial};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }
@@ -620,6 +620,9 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     if (e == hipSuccess) e = upload(&p->bcell, bcell, &p->bytes, s);
     if (e == hipSuccess) e = upload(&p->bverts, bverts, &p->bytes, s);
     if (!is_mat) {
+        const size_t rb = sizeof(double) * (size_t)femk::reduce_partials(ncells);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->red_partial, rb ? rb : 8);
+        if (e == hipSuccess) p->bytes += rb;
         std::vector<int32_t> inc32(nrows + 1);
         for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
         if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
@@ -839,6 +842,48 @@ fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, con
     a.out2 = g_u && g_kappa ? g_kappa->data : nullptr;
     hipError_t e = femk::launch_nl(a, mode, fp32, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "assemble_adjoint launch");
+    return FEM_OK;
+}
+
+fem_status fem_par_loop_reduce(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                               const fem_dat *x, fem_global *g, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (form->kind == FEM_NL_RESIDUAL || form->kind == FEM_ELASTICITY)
+        return fail(ctx, FEM_E_UNSUPPORTED, "reduce: the form kind has no cell reduction");
+    const bool energy = form->kind != FEM_SOURCE;
+    const bool need_k = form->kind != FEM_MASS;
+    if ((st = check_args(ctx, form, args, need_k)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
+    if (!g || !g->data) return fail(ctx, FEM_E_ARG, "reduce: Global without data");
+    if (acc != FEM_SUM && acc != FEM_MIN && acc != FEM_MAX)
+        return fail(ctx, FEM_E_ARG, "reduce: a Global accepts SUM, MIN or MAX");
+    if (energy && !dat_ok(x, args->cell_node->to, 1))
+        return fail(ctx, FEM_E_ARG, "reduce: the energy needs x, a Dat on the nodes");
+    femk::AsmArgs a = base_args(plan, args);
+    form_coeffs(energy ? form->kind : FEM_MASS, &a.cstiff, &a.cmass);
+    a.coeff = need_k ? args->coeff[0]->data : args->coords->data;   // unread when cstiff == 0
+    a.x = energy ? x->data : nullptr;
+    const int mode = acc == FEM_SUM ? 0 : acc == FEM_MIN ? 1 : 2;
+    hipError_t e = femk::launch_reduce(a, plan->red_partial, mode, energy, g->data, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+    return FEM_OK;
+}
+
+fem_status fem_apply_dirichlet(fem_ctx *ctx, const fem_sparsity *sp, double *values, const uint8_t *mask,
+                               double diag, double *b, const double *g)
+{
+    if (!ctx) return FEM_E_ARG;
+    if (!sp || !sp->row_ptr || (!sp->col_idx && sp->nnz > 0) || sp->nrows < 0)
+        return fail(ctx, FEM_E_ARG, "apply_dirichlet: malformed sparsity");
+    if (sp->nrows != sp->ncols) return fail(ctx, FEM_E_ARG, "apply_dirichlet: the Mat must be square");
+    if ((!values && sp->nnz > 0) || (!mask && sp->nrows > 0))
+        return fail(ctx, FEM_E_ARG, "apply_dirichlet: values and mask are required");
+    if (g && !b) return fail(ctx, FEM_E_ARG, "apply_dirichlet: boundary values need a right-hand side");
+    hipError_t e = femk::launch_dirichlet(sp, values, mask, diag, b, g, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "apply_dirichlet launch");
     return FEM_OK;
 }
 

@@ -46,6 +46,7 @@ struct fem_plan {
     int64_t stream_entries = 0;  // Mat plans: 16-bit stream entries (padding included)
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
     int32_t max_blk_cells = 0;   // most cells any block gathers
+    double *red_partial = nullptr;  // Dat plans: one partial per 1024 cells (Global reductions)
     // Elasticity plans (is_mat == 2): per node pair of the node sparsity (a
     // 3x3 block of the vector CSR), its contributions in ascending cell id,
     // and the element-block workspace [ncells][55][9] (float64 for FEM_FP64,
@@ -112,6 +113,16 @@ hipError_t launch_action(const AsmArgs &a, hipStream_t s);
 // lambda = aux; 3: both, into out and out2); P1 Dat plans; fp32 selects
 // binary32 arithmetic.
 hipError_t launch_nl(const AsmArgs &a, int mode, bool fp32, hipStream_t s);
+
+// Global reductions over the cells (fem_global.hip): SUM / MIN / MAX (mode
+// 0 / 1 / 2) of the cell energies x_K^T A_K x_K (energy) or of the integrals
+// of f = coeff (not energy) into g[0]; partial holds reduce_partials(ncells).
+int64_t reduce_partials(int64_t ncells);
+hipError_t launch_reduce(const AsmArgs &a, double *partial, int mode, bool energy, double *g, hipStream_t s);
+
+// Dirichlet rows and columns (fem_bc.hip).
+hipError_t launch_dirichlet(const fem_sparsity *sp, double *values, const uint8_t *mask, double diag, double *b,
+                            const double *g, hipStream_t s);
 
 // Vector P2 linear elasticity (fem_elast.hip): argument checks, plan and
 // assembly (element blocks by MFMA, then the pull into the CSR).

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfem.so")
 FEM_OK, FEM_E_ARG, FEM_E_RANGE, FEM_E_OVERFLOW, FEM_E_UNSUPPORTED, FEM_E_NOMEM, FEM_E_DEVICE = range(7)
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_E_ARG", 2: "FEM_E_RANGE", 3: "FEM_E_OVERFLOW",
                 4: "FEM_E_UNSUPPORTED", 5: "FEM_E_NOMEM", 6: "FEM_E_DEVICE"}
-FEM_READ, FEM_WRITE, FEM_INC = 0, 1, 2
+FEM_READ, FEM_WRITE, FEM_INC, FEM_SUM, FEM_MIN, FEM_MAX = 0, 1, 2, 3, 4, 5
 FEM_TRIANGLE, FEM_TETRAHEDRON = 2, 3
 FEM_FP64, FEM_FP32, FEM_BF16, FEM_FP16 = 0, 1, 2, 3
 FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE, FEM_NL_RESIDUAL, FEM_ELASTICITY = 0, 1, 2, 3, 4, 5
@@ -56,6 +56,10 @@ class fem_mat(C.Structure):
     _fields_ = [("sp", C.POINTER(fem_sparsity)), ("values", C.c_void_p)]
 
 
+class fem_global(C.Structure):
+    _fields_ = [("data", C.c_void_p)]
+
+
 class fem_form(C.Structure):
     _fields_ = [("kind", C.c_int), ("cell", C.c_int), ("degree", C.c_int32),
                 ("dim", C.c_int32), ("prec", C.c_int)]
@@ -74,7 +78,8 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
-           "fem_server_configure", "fem_server_take_completed"]
+           "fem_server_configure", "fem_server_take_completed", "fem_par_loop_reduce",
+           "fem_apply_dirichlet"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
@@ -108,6 +113,9 @@ def lib():
                                                     C.POINTER(fem_dat), C.POINTER(fem_dat), C.POINTER(fem_dat),
                                                     C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
+        L.fem_apply_dirichlet.argtypes = [P, C.POINTER(fem_sparsity), P, P, C.c_double, P, P]
+        L.fem_par_loop_reduce.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_dat),
+                                          C.POINTER(fem_global), C.c_int]
         L.fem_expand_sparsity.argtypes = [P, C.POINTER(fem_sparsity), C.c_int32, C.POINTER(fem_sparsity)]
         I64p = C.POINTER(C.c_int64)
         L.fem_server_create.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(P)]
@@ -302,6 +310,20 @@ def fem_par_loop_assemble_adjoint(ctx: Context, plan: Plan, frm: fem_form, args:
     ctx.check(lib().fem_par_loop_assemble_adjoint(ctx.h, plan.h, C.byref(frm), C.byref(args.c), C.byref(dl),
                                                   C.byref(du) if du is not None else None,
                                                   C.byref(dk) if dk is not None else None, acc))
+
+
+def fem_par_loop_reduce(ctx: Context, plan: Plan, frm: fem_form, args: Args, x, g, acc: int = FEM_SUM):
+    """g: a one-element float64 device tensor (the Global)."""
+    dx = fem_dat(C.pointer(args.nodes), 1, _ptr(x)) if x is not None else None
+    gg = fem_global(_ptr(g))
+    ctx.check(lib().fem_par_loop_reduce(ctx.h, plan.h, C.byref(frm), C.byref(args.c),
+                                        C.byref(dx) if dx is not None else None, C.byref(gg), acc))
+
+
+def fem_apply_dirichlet(ctx: Context, sp: Sparsity, values, mask, diag: float = 1.0, b=None, g=None):
+    """mask: uint8 device tensor over the rows; b, g: float64 device tensors or None."""
+    ctx.check(lib().fem_apply_dirichlet(ctx.h, C.byref(sp.c), _ptr(values), _ptr(mask), diag,
+                                        _ptr(b) if b is not None else None, _ptr(g) if g is not None else None))
 
 
 def fem_renumber(ctx: Context, frm: fem_form, args: Args):
