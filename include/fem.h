@@ -316,6 +316,28 @@ fem_status fem_par_loop_reduce(fem_ctx *ctx, const fem_plan *plan, const fem_for
                                const fem_dat *x, fem_global *g, fem_access acc);
 
 /*
+ * Mixed function spaces by blocks ("Factorisation of mixed function spaces"):
+ * a bilinear form on W = V^nfields (nfields copies of the scalar space of
+ * `form` -- cell, degree; its kind is ignored) is split into its (test field
+ * a, trial field b) parts, each of which is assembled by the scalar kernel
+ * into its own Mat, mats[a*nfields + b] (a nested matrix; a block whose
+ * values are NULL is zero and skipped).  Block (a, b) is
+ *   blocks[a*nfields + b].scale * (the form of blocks[..].kind),
+ * kind FEM_MASS, FEM_LAPLACE or FEM_HELMHOLTZ, with its own P1 coefficient
+ * Dat (kappa of the stiffness term; NULL only for FEM_MASS).  Every block
+ * shares the scalar sparsity and the Mat plan of (form, args, sp).  The
+ * monolithic matrix over DOF f*nnodes + node is the block matrix of these.
+ * Asynchronous; allocates nothing.
+ */
+typedef struct fem_block {
+    fem_kind kind;
+    double scale;
+    const fem_dat *coeff;
+} fem_block;
+fem_status fem_par_loop_assemble_mixed(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                                       int32_t nfields, const fem_block *blocks, fem_mat *mats, fem_access acc);
+
+/*
  * Dirichlet boundary conditions on an assembled system, in place (the paper's
  * Firedrake example assembles A with a DirichletBC and applies it to b).  For
  * every row r with mask[r] != 0: row r and column r of A become zero except

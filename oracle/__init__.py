@@ -7,7 +7,8 @@ sparsity; and the nonlinear residual kappa grad(u).grad(v) + u^3 v - f v with
 its vector-Jacobian products (the adjoint assembly); and vector Lagrange
 linear elasticity 2 mu eps(u):eps(v) + lam div(u) div(v) on per-cell
 coordinates (the precision benchmark); and per-cell contributions to Global
-reductions (cell energies x_K^T A_K x_K, integrals of f).  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+reductions (cell energies x_K^T A_K x_K, integrals of f); the monolithic
+matrix of a form on a mixed space.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The product library never does.
 
 Every function here follows the paper's definition of a parallel loop over
@@ -72,6 +73,8 @@ def lib():
         L.oracle_nl_residual.restype = I
         L.oracle_nl_adjoint.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P, P, P]
         L.oracle_nl_adjoint.restype = I
+        L.oracle_mixed_mat.argtypes = [I, I, I, L64, P, P, P, L64, P, P, P, P, P, P, P]
+        L.oracle_mixed_mat.restype = I
         L.oracle_cell_values.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, P, P, P, P]
         L.oracle_cell_values.restype = I
         L.oracle_elasticity_element.argtypes = [I, I, P, P, P, P, P]
@@ -368,3 +371,26 @@ def apply_dirichlet(row_ptr, col_idx, values, b, mask, g=None, diag=1.0):
             bb[r] = diag * gg[r]
             babs[r] = abs(bb[r])
     return vals, bb, babs
+
+
+def mixed_mat(dim, degree, cell_vertex, coords, cell_node, nnodes, blocks):
+    """Monolithic matrix of a form on V^nf: blocks[a][b] = (cstiff, cmass, kappa or None)
+    for test field a and trial field b.  Returns (row_ptr, col_idx, values, abs)
+    over the DOFs f*nnodes + node, with the oracle's own sparsity."""
+    nf = len(blocks)
+    cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
+    n = cn.shape[1]
+    mixed_map = np.concatenate([cn + f * nnodes for f in range(nf)], axis=1).astype(np.int32)
+    rp, ci = sparsity(mixed_map, nf * nnodes)
+    cs = np.array([blocks[a][b][0] for a in range(nf) for b in range(nf)], dtype=np.float64)
+    cm = np.array([blocks[a][b][1] for a in range(nf) for b in range(nf)], dtype=np.float64)
+    kaps = [None if blocks[a][b][2] is None else _c(blocks[a][b][2], np.float64)
+            for a in range(nf) for b in range(nf)]
+    kp = (C.c_void_p * (nf * nf))(*[None if k is None else k.ctypes.data for k in kaps])
+    vals = np.zeros(max(int(rp[-1]), 1)); absv = np.zeros_like(vals)
+    rc = lib().oracle_mixed_mat(dim, degree, nf, cv.shape[0], _p(cv), _p(X), _p(cn), nnodes,
+                                C.cast(kp, C.c_void_p), _p(cs), _p(cm), _p(rp), _p(ci), _p(vals), _p(absv))
+    if rc:
+        raise RuntimeError(f"oracle mixed_mat failed ({rc})")
+    nnz = int(rp[-1])
+    return rp, ci, vals[:nnz], absv[:nnz]

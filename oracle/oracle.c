@@ -1039,3 +1039,59 @@ int oracle_cell_values(int kind, int dim, int degree, int64_t ncells, const int3
     *sum = s; *sum_abs = sa;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Mixed function spaces: the monolithic matrix                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The monolithic matrix of a bilinear form on the mixed space W = V^nf (nf
+ * copies of the scalar P_k space V, DOF f*nnodes + node for field f) whose
+ * (test field a, trial field b) part is  cstiff[a*nf+b] kappa_ab
+ * grad(u_b).grad(v_a) + cmass[a*nf+b] u_b v_a,  kappa_ab the P1 vertex field
+ * kap[a*nf+b] (NULL: 1).  The mixed element matrix of each cell is formed
+ * over the combined basis (field-major local order) and added entry by entry
+ * into the monolithic CSR row_ptr/col_idx (rows nf*nnodes), cells in index
+ * order.  This is the single mixed kernel and monolithic matrix that the
+ * paper contrasts with Firedrake's split, per-block assembly.
+ */
+int oracle_mixed_mat(int dim, int degree, int nf, int64_t ncells, const int32_t *cell_vertex, const double *coords,
+                     const int32_t *cell_node, int64_t nnodes, const double *const *kap, const double *cstiff,
+                     const double *cmass, const int64_t *row_ptr, const int32_t *col_idx, double *values,
+                     double *absval)
+{
+    const int n = oracle_nloc(dim, degree), nv = dim + 1, NN = nf * n;
+    if (n < 0 || nf < 1 || nf > 4) return -1;
+    const int64_t nnz = row_ptr[nf * nnodes];
+    memset(values, 0, sizeof(double) * (size_t)nnz);
+    memset(absval, 0, sizeof(double) * (size_t)nnz);
+    double *A = malloc(sizeof(double) * NN * NN), *Aa = malloc(sizeof(double) * NN * NN);
+    double Ab[MAXLOC * MAXLOC], Aab[MAXLOC * MAXLOC], xv[12], kv[4], dummy[4];
+    int rc = 0;
+    if (!A || !Aa) rc = -1;
+    for (int64_t c = 0; c < ncells && !rc; ++c) {
+        gather_cell(dim, c, cell_vertex, coords, NULL, xv, dummy);
+        for (int a = 0; a < nf && !rc; ++a)
+            for (int b = 0; b < nf && !rc; ++b) {
+                const double *kf = kap[a * nf + b];
+                for (int m = 0; m < nv; ++m) kv[m] = kf ? kf[cell_vertex[c * nv + m]] : 1.0;
+                if (oracle_element_matrix(dim, degree, xv, kv, cstiff[a * nf + b], cmass[a * nf + b], Ab, Aab)) rc = -1;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        A[(int64_t)(a * n + i) * NN + b * n + j] = Ab[i * n + j];
+                        Aa[(int64_t)(a * n + i) * NN + b * n + j] = Aab[i * n + j];
+                    }
+            }
+        for (int I = 0; I < NN && !rc; ++I) {
+            const int64_t r = (I / n) * nnodes + cell_node[c * n + I % n];
+            for (int J = 0; J < NN; ++J) {
+                const int64_t k = find_col(row_ptr, col_idx, r, (int32_t)((J / n) * nnodes + cell_node[c * n + J % n]));
+                if (k < 0) { rc = -3; break; }
+                values[k] += A[(int64_t)I * NN + J];
+                absval[k] += Aa[(int64_t)I * NN + J];
+            }
+        }
+    }
+    free(A); free(Aa);
+    return rc;
+}

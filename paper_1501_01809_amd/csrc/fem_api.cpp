@@ -872,6 +872,45 @@ fem_status fem_par_loop_reduce(fem_ctx *ctx, const fem_plan *plan, const fem_for
     return FEM_OK;
 }
 
+fem_status fem_par_loop_assemble_mixed(fem_ctx *ctx, const fem_plan *plan, const fem_form *form, const fem_args *args,
+                                       int32_t nfields, const fem_block *blocks, fem_mat *mats, fem_access acc)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_form(ctx, form);
+    if (st != FEM_OK) return st;
+    if (nfields < 1 || nfields > 8 || !blocks || !mats)
+        return fail(ctx, FEM_E_ARG, "assemble_mixed: 1..8 fields with blocks and Mats");
+    if ((st = check_args(ctx, form, args, false)) != FEM_OK) return st;
+    if ((st = check_plan(ctx, plan, form, args, true)) != FEM_OK) return st;
+    if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "a Mat accepts only WRITE or INC");
+    for (int32_t q = 0; q < nfields * nfields; ++q) {         // validate every block before queuing any
+        const fem_block &bk = blocks[q];
+        if (!mats[q].values) continue;
+        if (bk.kind != FEM_MASS && bk.kind != FEM_LAPLACE && bk.kind != FEM_HELMHOLTZ)
+            return fail(ctx, FEM_E_ARG, "assemble_mixed: block %d must be a mass, Laplace or Helmholtz form", q);
+        if (bk.kind != FEM_MASS && !dat_ok(bk.coeff, args->cell_vertex->to, 1))
+            return fail(ctx, FEM_E_ARG, "assemble_mixed: block %d needs a P1 coefficient Dat", q);
+        if (!mats[q].sp || mats[q].sp->row_ptr != plan->row_ptr || mats[q].sp->nnz != plan->nnz)
+            return fail(ctx, FEM_E_ARG, "assemble_mixed: block %d's sparsity differs from the plan's", q);
+    }
+    for (int32_t q = 0; q < nfields * nfields; ++q) {
+        const fem_block &bk = blocks[q];
+        if (!mats[q].values) continue;
+        femk::AsmArgs a = base_args(plan, args);
+        form_coeffs(bk.kind, &a.cstiff, &a.cmass);
+        a.cstiff *= bk.scale;
+        a.cmass *= bk.scale;
+        a.coeff = bk.kind != FEM_MASS ? bk.coeff->data : args->coords->data;   // unread when cstiff == 0
+        a.row_ptr = mats[q].sp->row_ptr;
+        a.out = mats[q].values;
+        a.inc = acc == FEM_INC;
+        a.num_cus = ctx->num_cus;
+        hipError_t e = femk::launch_mat(a, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "assemble_mixed launch");
+    }
+    return FEM_OK;
+}
+
 fem_status fem_apply_dirichlet(fem_ctx *ctx, const fem_sparsity *sp, double *values, const uint8_t *mask,
                                double diag, double *b, const double *g)
 {

@@ -60,6 +60,10 @@ class fem_global(C.Structure):
     _fields_ = [("data", C.c_void_p)]
 
 
+class fem_block(C.Structure):
+    _fields_ = [("kind", C.c_int), ("scale", C.c_double), ("coeff", C.POINTER(fem_dat))]
+
+
 class fem_form(C.Structure):
     _fields_ = [("kind", C.c_int), ("cell", C.c_int), ("degree", C.c_int32),
                 ("dim", C.c_int32), ("prec", C.c_int)]
@@ -79,7 +83,7 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
            "fem_server_configure", "fem_server_take_completed", "fem_par_loop_reduce",
-           "fem_apply_dirichlet"]
+           "fem_apply_dirichlet", "fem_par_loop_assemble_mixed"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
@@ -113,6 +117,8 @@ def lib():
                                                     C.POINTER(fem_dat), C.POINTER(fem_dat), C.POINTER(fem_dat),
                                                     C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
+        L.fem_par_loop_assemble_mixed.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.c_int32,
+                                                  C.POINTER(fem_block), C.POINTER(fem_mat), C.c_int]
         L.fem_apply_dirichlet.argtypes = [P, C.POINTER(fem_sparsity), P, P, C.c_double, P, P]
         L.fem_par_loop_reduce.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_dat),
                                           C.POINTER(fem_global), C.c_int]
@@ -318,6 +324,30 @@ def fem_par_loop_reduce(ctx: Context, plan: Plan, frm: fem_form, args: Args, x, 
     gg = fem_global(_ptr(g))
     ctx.check(lib().fem_par_loop_reduce(ctx.h, plan.h, C.byref(frm), C.byref(args.c),
                                         C.byref(dx) if dx is not None else None, C.byref(gg), acc))
+
+
+def fem_par_loop_assemble_mixed(ctx: Context, plan: Plan, frm: fem_form, args: Args, blocks, values, sp: Sparsity,
+                                acc: int = FEM_WRITE):
+    """blocks: nf x nf list of (kind name, scale, coefficient tensor or None), or None
+    for a zero block; values: nf x nf list of float64 device tensors (None for zero
+    blocks).  Every block shares sp and the Mat plan."""
+    nf = len(blocks)
+    bl = (fem_block * (nf * nf))()
+    ms = (fem_mat * (nf * nf))()
+    keep = []
+    for a in range(nf):
+        for b in range(nf):
+            q = a * nf + b
+            spec, vals = blocks[a][b], values[a][b]
+            if spec is None or vals is None:
+                ms[q] = fem_mat(C.pointer(sp.c), None)
+                continue
+            kind, scale, coeff = spec
+            d = fem_dat(C.pointer(args.verts), 1, _ptr(coeff)) if coeff is not None else None
+            keep.append(d)
+            bl[q] = fem_block(KINDS[kind], scale, C.pointer(d) if d is not None else None)
+            ms[q] = fem_mat(C.pointer(sp.c), _ptr(vals))
+    ctx.check(lib().fem_par_loop_assemble_mixed(ctx.h, plan.h, C.byref(frm), C.byref(args.c), nf, bl, ms, acc))
 
 
 def fem_apply_dirichlet(ctx: Context, sp: Sparsity, values, mask, diag: float = 1.0, b=None, g=None):

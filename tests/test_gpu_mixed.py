@@ -1,0 +1,68 @@
+"""Mixed-space assembly by blocks (nested Mats) against the oracle's
+monolithic mixed matrix."""
+import numpy as np
+import pytest
+
+import fem_inputs as fi
+import oracle
+from fem_case import TOL, make_case
+
+
+def check_rows(got, ref, absref, ptr, what):
+    """Per row: max |gpu - oracle| <= TOL * max_j S_rj, and the Frobenius bar.
+    Pure stiffness blocks have entries whose integrand vanishes identically
+    on axis-aligned boundary cells: the oracle's term scale S is exactly zero
+    there while the metric-form contraction leaves a rounding residue of the
+    order of the row's terms, so the bar is taken row-relative."""
+    for r in range(len(ptr) - 1):
+        a, b = ptr[r], ptr[r + 1]
+        if b > a:
+            e = np.max(np.abs(got[a:b] - ref[a:b]))
+            assert e <= TOL * np.max(absref[a:b]) + 1e-300, f"{what}: row {r}"
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref) + 1e-300, f"{what}: Frobenius"
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind,n,degree,nf", [("square", 8, 1, 2), ("square", 5, 2, 3), ("cube", 3, 2, 2),
+                                               ("cube", 2, 3, 2)])
+def test_blocks_equal_the_monolithic_matrix(kind, n, degree, nf):
+    import torch
+    from paper_1501_01809_amd import fem as F
+    case = make_case(kind, n, degree, seed=55, shuffle=True)
+    N = case.nnodes
+    st = fi.spawn_streams(56)
+    kap2 = fi.field(st["mu"], case.coords.shape[0], 0.5, 2.0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ctx = F.Context(0)
+    cv, X, cn = t(case.cells), t(case.coords), t(case.cell_node)
+    gk, gk2 = t(case.kappa), t(kap2)
+    args = F.Args(cv, X, cn, N, [gk])
+    sp = F.fem_build_sparsity(ctx, cn, N)
+    frm = F.form("helmholtz", case.dim, degree)
+    plan = F.fem_plan_create(ctx, frm, args, sp)
+    # a Cahn-Hilliard-type system (mass, dt K(kappa); -lam K(1)... ), a zero block when nf = 3
+    dt, lam = 0.25, 0.01
+    spec = {(0, 0): ("mass", 1.0, None), (0, 1): ("laplace", dt, gk), (1, 0): ("helmholtz", -lam, gk2),
+            (1, 1): ("mass", 1.0, None), (2, 2): ("helmholtz", 2.0, gk), (2, 0): ("laplace", 0.5, gk2)}
+    blocks = [[spec.get((a, b)) for b in range(nf)] for a in range(nf)]
+    nnz = int(sp.col_idx.numel())
+    vals = [[torch.empty(nnz, dtype=torch.float64, device="cuda") if blocks[a][b] else None for b in range(nf)]
+            for a in range(nf)]
+    F.fem_par_loop_assemble_mixed(ctx, plan, frm, args, blocks, vals, sp)
+    F.fem_sync(ctx)
+    host = {"mass": (0.0, 1.0), "laplace": (1.0, 0.0), "helmholtz": (1.0, 1.0)}
+    kmap = {id(gk): case.kappa, id(gk2): kap2}
+    oblocks = [[(0.0, 0.0, None) if blocks[a][b] is None else
+                (host[blocks[a][b][0]][0] * blocks[a][b][1], host[blocks[a][b][0]][1] * blocks[a][b][1],
+                 None if blocks[a][b][2] is None else kmap[id(blocks[a][b][2])]) for b in range(nf)] for a in range(nf)]
+    rp, ci, v, ab = oracle.mixed_mat(case.dim, degree, case.cells, case.coords, case.cell_node, N, oblocks)
+    srp = sp.row_ptr.cpu().numpy()
+    lens = np.diff(srp)
+    for a in range(nf):
+        for b in range(nf):
+            # block (a, b) of the monolithic row a*N + r: its b-th run of len(r) columns
+            idx = np.concatenate([np.arange(rp[a * N + r] + b * lens[r], rp[a * N + r] + (b + 1) * lens[r])
+                                  for r in range(N)])
+            got = vals[a][b].cpu().numpy() if vals[a][b] is not None else np.zeros(nnz)
+            check_rows(got, v[idx], ab[idx], srp, f"block ({a},{b})")
