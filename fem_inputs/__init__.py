@@ -14,10 +14,10 @@ benchmark shapes (unit square and unit cube, experiments section).
 from .meshes import (Mesh, unit_square, unit_cube, two_triangles, two_tets,
                      jitter_interior, node_map, permute_cells, permute_nodes,
                      permute_vertices, local_node_barycentrics, dg_coordinates,
-                     flatten_cells, boundary_nodes)
+                     flatten_cells, boundary_nodes, exterior_facets)
 from .fields import field, seeds, spawn_streams
 
 __all__ = ["Mesh", "unit_square", "unit_cube", "two_triangles", "two_tets",
            "jitter_interior", "node_map", "permute_cells", "permute_nodes",
            "permute_vertices", "local_node_barycentrics", "dg_coordinates",
-           "flatten_cells", "boundary_nodes", "field", "seeds", "spawn_streams"]
+           "flatten_cells", "boundary_nodes", "exterior_facets", "field", "seeds", "spawn_streams"]

@@ -171,6 +171,43 @@ def boundary_nodes(mesh: Mesh, cell_node: np.ndarray, degree: int) -> np.ndarray
     return np.any((pos <= 1e-12) | (pos >= 1 - 1e-12), axis=1).astype(np.uint8)
 
 
+def exterior_facets(mesh: Mesh, cell_node: np.ndarray, degree: int):
+    """Exterior facets of a unit square or cube mesh and their Maps.
+
+    A facet (the cell's vertices but one) is exterior when all its vertices
+    share a coordinate equal to 0 or 1 (jitter leaves the boundary alone).
+    Returns (facet_vertex int32 [F][d], facet_node int32 [F][nloc of the
+    degree-k (d-1)-simplex]): the facet's vertices in the cell's local order,
+    and its nodes in the facet's own local order (vertices, edges with the
+    two P3 nodes from the lower vertex, the P3 triangle's face node), taken
+    from the cell's nodes with the same barycentric weights.
+    """
+    d = mesh.dim
+    W = local_node_barycentrics(d, degree)
+    Wf = local_node_barycentrics(d - 1, degree)
+    key = {tuple(r): i for i, r in enumerate(W.tolist())}
+    fv, fn = [], []
+    X = mesh.coords
+    for c in range(mesh.ncells):
+        cv = mesh.cells[c]
+        for o in range(d + 1):
+            loc = [m for m in range(d + 1) if m != o]
+            P = X[cv[loc]]
+            on = any(np.all(np.abs(P[:, a] - v) <= 1e-12) for a in range(d) for v in (0.0, 1.0))
+            if not on:
+                continue
+            fv.append(cv[loc])
+            nodes = []
+            for wf in Wf.tolist():
+                w = [0] * (d + 1)
+                for j, m in enumerate(loc):
+                    w[m] = wf[j]
+                nodes.append(cell_node[c, key[tuple(w)]])
+            fn.append(nodes)
+    return (np.ascontiguousarray(np.array(fv, dtype=np.int32).reshape(-1, d)),
+            np.ascontiguousarray(np.array(fn, dtype=np.int32).reshape(len(fn), -1)))
+
+
 def local_node_barycentrics(dim: int, degree: int) -> np.ndarray:
     """Integer barycentric weights (rows sum to ``degree``) of the local nodes."""
     nv = dim + 1

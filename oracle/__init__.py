@@ -8,7 +8,7 @@ its vector-Jacobian products (the adjoint assembly); and vector Lagrange
 linear elasticity 2 mu eps(u):eps(v) + lam div(u) div(v) on per-cell
 coordinates (the precision benchmark); and per-cell contributions to Global
 reductions (cell energies x_K^T A_K x_K, integrals of f); the monolithic
-matrix of a form on a mixed space.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+matrix of a form on a mixed space; exterior facet integrals of g v.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The product library never does.
 
 Every function here follows the paper's definition of a parallel loop over
@@ -73,6 +73,8 @@ def lib():
         L.oracle_nl_residual.restype = I
         L.oracle_nl_adjoint.argtypes = [I, L64, P, P, P, L64, P, P, P, P, P, P, P]
         L.oracle_nl_adjoint.restype = I
+        L.oracle_facet_vec.argtypes = [I, I, L64, P, P, P, P, L64, P, P]
+        L.oracle_facet_vec.restype = I
         L.oracle_mixed_mat.argtypes = [I, I, I, L64, P, P, P, L64, P, P, P, P, P, P, P]
         L.oracle_mixed_mat.restype = I
         L.oracle_cell_values.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, P, P, P, P]
@@ -394,3 +396,14 @@ def mixed_mat(dim, degree, cell_vertex, coords, cell_node, nnodes, blocks):
         raise RuntimeError(f"oracle mixed_mat failed ({rc})")
     nnz = int(rp[-1])
     return rp, ci, vals[:nnz], absv[:nnz]
+
+
+def facet_vec(dim, degree, facet_vertex, coords, facet_node, g, nrows):
+    """b_i = sum over the given facets of the integral of g v_i ds (P1 g)."""
+    fv = _c(facet_vertex, np.int32); X = _c(coords, np.float64); fn = _c(facet_node, np.int32)
+    gg = _c(g, np.float64)
+    b = np.zeros(nrows); ab = np.zeros(nrows)
+    rc = lib().oracle_facet_vec(dim, degree, fv.shape[0], _p(fv), _p(X), _p(fn), _p(gg), nrows, _p(b), _p(ab))
+    if rc:
+        raise RuntimeError(f"oracle facet_vec failed ({rc})")
+    return b, ab

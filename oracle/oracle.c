@@ -124,6 +124,11 @@ int oracle_gauss_jacobi(int n, int alpha, double *t, double *w)
 int oracle_simplex_rule(int dim, int q, double *pts, double *wts)
 {
     double t1[MAXQ], w1[MAXQ], t2[MAXQ], w2[MAXQ], t3[MAXQ], w3[MAXQ];
+    if (dim == 1) {                      /* the segment [0, 1]: Gauss-Legendre */
+        if (oracle_gauss_jacobi(q, 0, t1, w1)) return -1;
+        for (int a = 0; a < q; ++a) { pts[a] = t1[a]; wts[a] = w1[a]; }
+        return q;
+    }
     if (dim == 2) {
         if (oracle_gauss_jacobi(q, 1, t1, w1) || oracle_gauss_jacobi(q, 0, t2, w2)) return -1;
         int k = 0;
@@ -160,6 +165,7 @@ int oracle_simplex_rule(int dim, int q, double *pts, double *wts)
 
 int oracle_nloc(int dim, int degree)
 {
+    if (dim == 1) return degree >= 1 && degree <= 3 ? degree + 1 : -1;
     if (dim == 2) return degree == 1 ? 3 : degree == 2 ? 6 : degree == 3 ? 10 : -1;
     if (dim == 3) return degree == 1 ? 4 : degree == 2 ? 10 : degree == 3 ? 20 : -1;
     return -1;
@@ -1094,4 +1100,66 @@ int oracle_mixed_mat(int dim, int degree, int nf, int64_t ncells, const int32_t 
     }
     free(A); free(Aa);
     return rc;
+}
+
+
+/* ------------------------------------------------------------------ */
+/* Exterior facet integrals                                            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * b_i = sum over exterior facets F of the integral over F of g v_i ds, g a P1
+ * field (vertex values), v_i the degree-k Lagrange basis restricted to F: the
+ * basis of the (dim-1)-simplex F in its own local order (facet vertices in
+ * the facet_vertex order, then edge nodes, then the P3 triangle's face
+ * node).  facet_vertex [nf][dim], facet_node [nf][nloc(dim-1, k)].
+ * Quadrature on the reference (dim-1)-simplex with the measure of F:
+ * integral over F = |F| (dim-1)! sum_q w_q h(xi_q).
+ */
+int oracle_facet_vec(int dim, int degree, int64_t nfacets, const int32_t *facet_vertex, const double *coords,
+                     const int32_t *facet_node, const double *g, int64_t nrows, double *b, double *babs)
+{
+    const int e = dim - 1, n = oracle_nloc(e, degree), nv = dim;
+    if (n < 0 || e < 1) return -1;
+    struct rule R;
+    if (make_rule(e, degree + 1, &R)) return -1;
+    memset(b, 0, sizeof(double) * (size_t)nrows);
+    memset(babs, 0, sizeof(double) * (size_t)nrows);
+    for (int64_t f = 0; f < nfacets; ++f) {
+        double x[3][3], gv[3];
+        for (int m = 0; m < nv; ++m) {
+            const int64_t v = facet_vertex[f * nv + m];
+            for (int r = 0; r < dim; ++r) x[m][r] = coords[v * dim + r];
+            gv[m] = g[v];
+        }
+        double meas;
+        if (e == 1) {
+            double s2 = 0.0;
+            for (int r = 0; r < dim; ++r) s2 += (x[1][r] - x[0][r]) * (x[1][r] - x[0][r]);
+            meas = sqrt(s2);
+        } else {
+            const double u[3] = {x[1][0] - x[0][0], x[1][1] - x[0][1], x[1][2] - x[0][2]};
+            const double w[3] = {x[2][0] - x[0][0], x[2][1] - x[0][1], x[2][2] - x[0][2]};
+            const double cx = u[1] * w[2] - u[2] * w[1], cy = u[2] * w[0] - u[0] * w[2], cz = u[0] * w[1] - u[1] * w[0];
+            meas = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+        }
+        const double scale = meas * (e == 2 ? 2.0 : 1.0);     /* |F| (dim-1)! */
+        for (int q = 0; q < R.np; ++q) {
+            double lam[4], phi[MAXLOC], dphi[MAXLOC * 4];
+            double s = 0.0;
+            for (int m = 0; m < e; ++m) { lam[m + 1] = R.pts[q * e + m]; s += lam[m + 1]; }
+            lam[0] = 1.0 - s;
+            oracle_basis(e, degree, lam, phi, dphi);
+            double gq = 0.0, ga = 0.0;
+            for (int m = 0; m < nv; ++m) { gq += gv[m] * lam[m]; ga += fabs(gv[m] * lam[m]); }
+            const double w = R.wts[q] * scale;
+            for (int i = 0; i < n; ++i) {
+                const int64_t r = facet_node[f * n + i];
+                if (r < 0 || r >= nrows) return -2;
+                b[r] += w * gq * phi[i];
+                babs[r] += fabs(w * phi[i]) * ga;
+            }
+        }
+    }
+    return 0;
 }
