@@ -338,6 +338,35 @@ fem_status fem_par_loop_assemble_mixed(fem_ctx *ctx, const fem_plan *plan, const
                                        int32_t nfields, const fem_block *blocks, fem_mat *mats, fem_access acc);
 
 /*
+ * Exterior facet integrals ("The mesh abstraction": the mesh's exterior
+ * facets are an iteration Set of the parallel loop, the source of their own
+ * Maps).  For a triangle mesh the facets are segments, for a tetrahedral mesh
+ * triangles.  facet_vertex: the facet's d vertices (arity d); facet_node: the
+ * nodes of the degree-k Lagrange element of the facet, in the facet's own
+ * local order (its vertices in facet_vertex order, then its edges in
+ * lexicographic order with the two P3 nodes from the lower vertex, then a P3
+ * triangle's face node); coords: the vertex Dat (dim d); g: a P1 vertex Dat.
+ * form: FEM_SOURCE with the mesh's cell and degree.
+ *   b[i] (+)= sum over facets F of the integral over F of g v_i ds.
+ * fem_facet_plan_create builds the node-to-facet incidence and a facet
+ * workspace (synchronises, allocates); fem_par_loop_assemble_facets runs one
+ * kernel over the facets and one over the node rows, summing each row in
+ * ascending facet id (deterministic, no atomics; asynchronous, allocates
+ * nothing; calls on one plan must not overlap).  b covers all nodes: WRITE
+ * zeroes the rows no facet touches.
+ */
+typedef struct fem_facets {
+    const fem_set *facets;
+    const fem_map *facet_vertex;
+    const fem_map *facet_node;
+    const fem_dat *coords;
+    const fem_dat *g;
+} fem_facets;
+fem_status fem_facet_plan_create(fem_ctx *ctx, const fem_form *form, const fem_facets *facets, fem_plan **plan);
+fem_status fem_par_loop_assemble_facets(fem_ctx *ctx, const fem_plan *plan, const fem_form *form,
+                                        const fem_facets *facets, fem_dat *b, fem_access acc);
+
+/*
  * Dirichlet boundary conditions on an assembled system, in place (the paper's
  * Firedrake example assembles A with a DirichletBC and applies it to b).  For
  * every row r with mask[r] != 0: row r and column r of A become zero except

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfem.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip", "fem_elast.hip", "fem_serve.cpp", "fem_global.hip", "fem_bc.hip"]
+SOURCES = ["fem_api.cpp", "fem_sparsity.hip", "fem_assemble.hip", "fem_nl.hip", "fem_elast.hip", "fem_serve.cpp", "fem_global.hip", "fem_bc.hip", "fem_facet.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,6 +41,9 @@ def build(verbose: bool = False) -> str:
                           stdout=subprocess.DEVNULL)
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_elast_tables.py"),
                            os.path.join(CSRC, "fem_elast_tables.h")],
+                          stdout=subprocess.DEVNULL)
+    subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_facet_tables.py"),
+                           os.path.join(CSRC, "fem_facet_tables.h")],
                           stdout=subprocess.DEVNULL)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))

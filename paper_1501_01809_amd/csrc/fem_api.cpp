@@ -142,7 +142,8 @@ void free_plan_arrays(fem_plan *p)
 {
     void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
                     p->blk_hdr, p->blk_w, p->wq, p->pstream,
-                    p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work, p->red_partial};
+                    p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work, p->red_partial,
+                    p->f_ptr, p->f_ent, p->f_work};
     for (void *q : arrs)
         if (q) (void)hipFree(q);
 }

@@ -47,6 +47,11 @@ struct fem_plan {
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
     int32_t max_blk_cells = 0;   // most cells any block gathers
     double *red_partial = nullptr;  // Dat plans: one partial per 1024 cells (Global reductions)
+    // Exterior facet plans (is_mat == 3; ncells = facets): node-to-facet
+    // incidence (entries f*nloc + l, ascending) and the facet vectors.
+    int64_t *f_ptr = nullptr;
+    int32_t *f_ent = nullptr;
+    double *f_work = nullptr;
     // Elasticity plans (is_mat == 2): per node pair of the node sparsity (a
     // 3x3 block of the vector CSR), its contributions in ascending cell id,
     // and the element-block workspace [ncells][55][9] (float64 for FEM_FP64,

@@ -60,6 +60,11 @@ class fem_global(C.Structure):
     _fields_ = [("data", C.c_void_p)]
 
 
+class fem_facets(C.Structure):
+    _fields_ = [("facets", C.POINTER(fem_set)), ("facet_vertex", C.POINTER(fem_map)),
+                ("facet_node", C.POINTER(fem_map)), ("coords", C.POINTER(fem_dat)), ("g", C.POINTER(fem_dat))]
+
+
 class fem_block(C.Structure):
     _fields_ = [("kind", C.c_int), ("scale", C.c_double), ("coeff", C.POINTER(fem_dat))]
 
@@ -83,7 +88,8 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
            "fem_server_configure", "fem_server_take_completed", "fem_par_loop_reduce",
-           "fem_apply_dirichlet", "fem_par_loop_assemble_mixed"]
+           "fem_apply_dirichlet", "fem_par_loop_assemble_mixed", "fem_facet_plan_create",
+           "fem_par_loop_assemble_facets"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
 
 _lib = None
@@ -117,6 +123,9 @@ def lib():
                                                     C.POINTER(fem_dat), C.POINTER(fem_dat), C.POINTER(fem_dat),
                                                     C.c_int]
         L.fem_renumber.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), P, P, P]
+        L.fem_facet_plan_create.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_facets), C.POINTER(P)]
+        L.fem_par_loop_assemble_facets.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_facets),
+                                                   C.POINTER(fem_dat), C.c_int]
         L.fem_par_loop_assemble_mixed.argtypes = [P, P, C.POINTER(fem_form), C.POINTER(fem_args), C.c_int32,
                                                   C.POINTER(fem_block), C.POINTER(fem_mat), C.c_int]
         L.fem_apply_dirichlet.argtypes = [P, C.POINTER(fem_sparsity), P, P, C.c_double, P, P]
@@ -348,6 +357,33 @@ def fem_par_loop_assemble_mixed(ctx: Context, plan: Plan, frm: fem_form, args: A
             bl[q] = fem_block(KINDS[kind], scale, C.pointer(d) if d is not None else None)
             ms[q] = fem_mat(C.pointer(sp.c), _ptr(vals))
     ctx.check(lib().fem_par_loop_assemble_mixed(ctx.h, plan.h, C.byref(frm), C.byref(args.c), nf, bl, ms, acc))
+
+
+class Facets:
+    """Exterior facet arguments over torch device tensors (references kept)."""
+
+    def __init__(self, facet_vertex, facet_node, coords, g, nnodes):
+        self.t = (facet_vertex, facet_node, coords, g)
+        self.fset = fem_set(facet_vertex.shape[0])
+        self.verts = fem_set(coords.shape[0])
+        self.nodes = fem_set(nnodes)
+        self.fv = fem_map(C.pointer(self.fset), C.pointer(self.verts), facet_vertex.shape[1], _ptr(facet_vertex))
+        self.fn = fem_map(C.pointer(self.fset), C.pointer(self.nodes), facet_node.shape[1], _ptr(facet_node))
+        self.X = fem_dat(C.pointer(self.verts), coords.shape[1], _ptr(coords))
+        self.g = fem_dat(C.pointer(self.verts), 1, _ptr(g))
+        self.c = fem_facets(C.pointer(self.fset), C.pointer(self.fv), C.pointer(self.fn), C.pointer(self.X),
+                            C.pointer(self.g))
+
+
+def fem_facet_plan_create(ctx: Context, frm: fem_form, fa: Facets) -> Plan:
+    h = C.c_void_p()
+    ctx.check(lib().fem_facet_plan_create(ctx.h, C.byref(frm), C.byref(fa.c), C.byref(h)))
+    return Plan(h, (fa,))
+
+
+def fem_par_loop_assemble_facets(ctx: Context, plan: Plan, frm: fem_form, fa: Facets, b, acc: int = FEM_WRITE):
+    d = fem_dat(C.pointer(fa.nodes), 1, _ptr(b))
+    ctx.check(lib().fem_par_loop_assemble_facets(ctx.h, plan.h, C.byref(frm), C.byref(fa.c), C.byref(d), acc))
 
 
 def fem_apply_dirichlet(ctx: Context, sp: Sparsity, values, mask, diag: float = 1.0, b=None, g=None):
