@@ -400,6 +400,70 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
     return out
 
 
+def bench_extras(ctx, d, g, sp, mplan, vplan, dim, degree, steps, warmup):
+    """The paper-adjacent steps on the main workload's mesh, each timed per
+    call with HIP events: the Global SUM of the cell energies x^T A x, the
+    Dirichlet rows and columns of the assembled system (boundary nodes of the
+    cube, lifted boundary values), the exterior facet integral of g v, and a
+    two-field mixed system by blocks (four Mats)."""
+    import torch
+    import fem_inputs as fi
+    from paper_1501_01809_amd import fem as F
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    def timeit(fn):
+        for _ in range(warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        return float(ms.mean()), float(ms.min())
+
+    C = d["cells"].shape[0]; N = d["N"]; V = d["coords"].shape[0]; nl = d["cn"].shape[1]
+    nnz = int(sp.col_idx.numel())
+    form = F.form("helmholtz", dim, degree)
+    args_k = F.Args(g["cv"], g["X"], g["cn"], N, [g["kappa"]])
+    out = {}
+    gl = torch.zeros(1, dtype=torch.float64, device=dev)
+    ms, mn = timeit(lambda: F.fem_par_loop_reduce(ctx, vplan, form, args_k, g["x"], gl, F.FEM_SUM))
+    by = 4 * C * (nl + dim + 1) + 8 * V * (dim + 1) + 8 * N
+    out["global_energy_sum"] = {"ms": ms, "ms_min": mn, "cells_per_s": C / (ms * 1e-3), "alg_bytes": by,
+                                "GBps": by / (ms * 1e-3) / 1e9}
+    mesh = fi.Mesh(dim, d["coords"], d["cells"])
+    mask = fi.boundary_nodes(mesh, d["cn"], degree)
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev)
+    F.fem_par_loop_assemble_mat(ctx, mplan, form, args_k, vals, sp)
+    b = torch.zeros(N, dtype=torch.float64, device=dev)
+    gv = t(np.where(mask == 1, 1.0, 0.0))
+    gm = t(mask)
+    ms, mn = timeit(lambda: F.fem_apply_dirichlet(ctx, sp, vals, gm, 1.0, b, gv))
+    by = 8 * (N + 1) + 4 * nnz + 16 * nnz + N + 24 * N
+    out["dirichlet"] = {"ms": ms, "ms_min": mn, "boundary_dofs": int(mask.sum()), "alg_bytes": by,
+                        "GBps": by / (ms * 1e-3) / 1e9}
+    fv, fn = fi.exterior_facets(mesh, d["cn"], degree)
+    fa = F.Facets(t(fv), t(fn), g["X"], g["f"], N)
+    src = F.form("source", dim, degree)
+    fplan = F.fem_facet_plan_create(ctx, src, fa)
+    bf = torch.empty(N, dtype=torch.float64, device=dev)
+    ms, mn = timeit(lambda: F.fem_par_loop_assemble_facets(ctx, fplan, src, fa, bf))
+    out["exterior_facets"] = {"ms": ms, "ms_min": mn, "facets": int(fv.shape[0]),
+                              "facets_per_s": fv.shape[0] / (ms * 1e-3)}
+    blocks = [[("mass", 1.0, None), ("laplace", 0.25, g["kappa"])],
+              [("laplace", -0.01, g["kappa"]), ("mass", 1.0, None)]]
+    bvals = [[torch.empty(nnz, dtype=torch.float64, device=dev) for _ in range(2)] for _ in range(2)]
+    ms, mn = timeit(lambda: F.fem_par_loop_assemble_mixed(ctx, mplan, form, args_k, blocks, bvals, sp))
+    out["mixed_2x2_blocks"] = {"ms": ms, "ms_min": mn, "cells_per_s": C / (ms * 1e-3)}
+    del bvals, vals
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,6 +484,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving workload (4096 requests on 30 resident models)")
     ap.add_argument("--serving-requests", type=int, default=4096)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the paper-adjacent steps (Global energy, Dirichlet rows, facets, mixed blocks)")
     ap.add_argument("--ops", default="mat,vec,action",
                     help="operations run in a step (a subset is for profiling the kernels one by one; "
                          "the reported metric needs all three)")
@@ -565,6 +631,8 @@ def main():
         "setup_ms": setup,
         "host": platform.node(),
     }
+    if not args.no_extras:
+        out["paper_adjacent"] = bench_extras(ctx, d, g, sp, mplan, vplan, dim, args.degree, args.steps, args.warmup)
     if not args.no_nl:
         out["differentiation"] = bench_nl(ctx, args.steps, args.warmup, args.seed)
     if not args.no_precision:

@@ -180,32 +180,38 @@ def exterior_facets(mesh: Mesh, cell_node: np.ndarray, degree: int):
     degree-k (d-1)-simplex]): the facet's vertices in the cell's local order,
     and its nodes in the facet's own local order (vertices, edges with the
     two P3 nodes from the lower vertex, the P3 triangle's face node), taken
-    from the cell's nodes with the same barycentric weights.
+    from the cell's nodes with the same barycentric weights.  Facets come in
+    (cell, opposite local vertex) order.
     """
     d = mesh.dim
     W = local_node_barycentrics(d, degree)
     Wf = local_node_barycentrics(d - 1, degree)
     key = {tuple(r): i for i, r in enumerate(W.tolist())}
-    fv, fn = [], []
     X = mesh.coords
-    for c in range(mesh.ncells):
-        cv = mesh.cells[c]
-        for o in range(d + 1):
-            loc = [m for m in range(d + 1) if m != o]
-            P = X[cv[loc]]
-            on = any(np.all(np.abs(P[:, a] - v) <= 1e-12) for a in range(d) for v in (0.0, 1.0))
-            if not on:
-                continue
-            fv.append(cv[loc])
-            nodes = []
-            for wf in Wf.tolist():
-                w = [0] * (d + 1)
-                for j, m in enumerate(loc):
-                    w[m] = wf[j]
-                nodes.append(cell_node[c, key[tuple(w)]])
-            fn.append(nodes)
-    return (np.ascontiguousarray(np.array(fv, dtype=np.int32).reshape(-1, d)),
-            np.ascontiguousarray(np.array(fn, dtype=np.int32).reshape(len(fn), -1)))
+    fvs, fns, order = [], [], []
+    for o in range(d + 1):
+        loc = [m for m in range(d + 1) if m != o]
+        P = X[mesh.cells[:, loc]]                                  # [C][d][d]
+        on = np.zeros(mesh.ncells, dtype=bool)
+        for a in range(d):
+            for v in (0.0, 1.0):
+                on |= np.all(np.abs(P[:, :, a] - v) <= 1e-12, axis=1)
+        cid = np.nonzero(on)[0]
+        # local node of the cell for every facet node (same weights, facet vertices -> loc)
+        sel = []
+        for wf in Wf.tolist():
+            w = [0] * (d + 1)
+            for j, m in enumerate(loc):
+                w[m] = wf[j]
+            sel.append(key[tuple(w)])
+        fvs.append(mesh.cells[cid][:, loc])
+        fns.append(cell_node[cid][:, sel])
+        order.append(cid * (d + 1) + o)
+    order = np.concatenate(order)
+    perm = np.argsort(order, kind="stable")
+    fv = np.concatenate(fvs)[perm]
+    fn = np.concatenate(fns)[perm]
+    return (np.ascontiguousarray(fv.astype(np.int32)), np.ascontiguousarray(fn.astype(np.int32)))
 
 
 def local_node_barycentrics(dim: int, degree: int) -> np.ndarray:
