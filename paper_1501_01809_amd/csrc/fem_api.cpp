@@ -421,7 +421,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
     // Mat plans: per-lane LDS index streams (see fem_plan)
     const int MW = 512, NW = MW / 64;
-    const int SCAP = lim.slot_cap, CCH = lim.cell_cap, NE = lim.ne;
+    const int SCAP = lim.slot_cap, CCH = lim.chunk_cells, NE = lim.ne;
     const int ZIDX = SCAP + CCH * NE;
     std::vector<int32_t> blk_w{0}, wq;
     std::vector<uint16_t> stream;

@@ -108,12 +108,12 @@ __device__ __forceinline__ T ldc(const T *p)
 constexpr int MWG = 512;
 constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1; };
-template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1; };
-template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1; };
-template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2; };
-template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4; };
-template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4; };
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 1; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 1; };
+template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1, MCH = 1; };
+template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 1; };
+template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4; };
+template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8; };
 
 // Dat and action kernels: workgroups of VWG lanes, KR rows per lane; the
 // per-cell local vectors of the whole block live in LDS (VLDS doubles, two
@@ -607,7 +607,8 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
         if (is_mat) {                                                             \
             out->rows_per_block = MatLds<D, K>::SCAP;                             \
             out->slot_cap = MatLds<D, K>::SCAP;                                   \
-            out->cell_cap = MatLds<D, K>::CCH;                                    \
+            out->cell_cap = MatLds<D, K>::CCH * MatCfg<D, K>::MCH;                \
+            out->chunk_cells = MatLds<D, K>::CCH;                                 \
         } else {                                                                  \
             out->rows_per_block = VKR * VWG;                                      \
             out->cell_cap = std::min(1 << (16 - lb), VLDS / nloc);                \

@@ -141,7 +141,8 @@ fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *fo
 struct Limits {
     int rows_per_block;     // rows a workgroup can own
     int slot_cap;           // Mat values a workgroup holds in LDS (Mat only)
-    int cell_cap;           // distinct cells per block (Mat: per chunk)
+    int cell_cap;           // distinct cells per block
+    int chunk_cells;        // Mat: cells whose element tensors share LDS at once (one chunk)
     int ne;                 // doubles per packed element tensor (Mat only)
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
