@@ -109,7 +109,7 @@ constexpr int MWG = 512;
 constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
 template <int D, int K> struct MatCfg;
 template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 1; };
-template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 1; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16; };
 template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1, MCH = 1; };
 template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 1; };
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4; };
