@@ -474,7 +474,7 @@ def main():
                     help="n^3 x 6 Kuhn tetrahedra (default) or n x n x 2 triangles")
     ap.add_argument("--degree", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1501)
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=40960)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-renumber", action="store_true")
     ap.add_argument("--no-nl", action="store_true",

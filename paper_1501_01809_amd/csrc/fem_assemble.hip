@@ -122,6 +122,17 @@ constexpr int VWG = 512;
 constexpr int VKR = 2;
 constexpr int VLDS = LDS_DOUBLES / 2;
 constexpr int VPRE = 8;     // entries of a row fetched per batch
+// Action: METRIC evaluates y_K = A_K x_K from the cstiff-scaled nodal kappa
+// and the metric, terms grouped by metric pair (act_t), instead of from the
+// (d+1) x NM products P (act): fewer live registers, a few more FMAs.  It
+// pays for P1 and P2 and not for P3 (the inner sums then crowd out the
+// registers).  PREFETCH gathers the next cell's inputs while the current one
+// is evaluated; the P2 tetrahedron drops it to stay within 128 VGPRs (four
+// waves per SIMD), which measured 125 against 153 us at 64^3 x 6 cells.
+template <int D, int K> struct ActCfg {
+    static constexpr bool METRIC = K <= 2;
+    static constexpr bool PREFETCH = !(D == 3 && K == 2);
+};
 
 template <int D, int K> struct TabOf;
 template <> struct TabOf<2, 1> { using T = femtab::Tab21; };
@@ -522,18 +533,7 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
     __shared__ double vk[CAP * NL];
     const int b = blockIdx.x, tid = threadIdx.x;
     const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
-    int cur[VKR], end[VKR];
-    uint32_t pe[VKR][VPRE];
-    double acc[VKR];
-#pragma unroll
-    for (int k = 0; k < VKR; ++k) {
-        const int r = r0 + tid + VWG * k;
-        cur[k] = r < r1 ? a.inc_ptr[r] : 0;
-        end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
-        acc[k] = 0.0;
-#pragma unroll
-        for (int m = 0; m < VPRE; ++m) pe[k][m] = cur[k] + m < end[k] ? a.ent[cur[k] + m] : 0u;
-    }
+    constexpr bool PRE = !ACTION || ActCfg<D, K>::PREFETCH;
     const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
     CellIn<D> cin;
     double xl[ACTION ? NL : 1];
@@ -545,23 +545,46 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
             for (int j = 0; j < NL; ++j) xl[j] = a.x[a.cell_node[cell * NL + j]];
         }
     };
-    if (tid < nc) fetch(tid);
+    if (PRE && tid < nc) fetch(tid);
     for (int cs = 0; cs < nc; cs += VWG) {
         if (cs + tid < nc) {
+            if (!PRE) fetch(cs + tid);
             double loc[NL];
             if constexpr (ACTION) {
-                double P[NP], madet;
-                tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
 #pragma unroll
                 for (int j = 0; j < NL; ++j) loc[j] = 0.0;
-                T::act(P, madet, xl, loc);
+                if constexpr (ActCfg<D, K>::METRIC) {
+                    double G[Geo<D>::NM], kc[D + 1];
+                    const double adet = Geo<D>::metric(cin.x, G);
+#pragma unroll
+                    for (int m = 0; m <= D; ++m) kc[m] = a.cstiff * cin.k[m];
+                    T::act_t(kc, G, a.cmass * adet, xl, loc);
+                } else {
+                    double P[NP], madet;
+                    tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
+                    T::act(P, madet, xl, loc);
+                }
             } else {
                 T::vec(cin.k, Geo<D>::absdet(cin.x), loc);
             }
 #pragma unroll
             for (int j = 0; j < NL; ++j) vk[(cs + tid) * NL + j] = loc[j];
         }
-        if (cs + VWG + tid < nc) fetch(cs + VWG + tid);
+        if (PRE && cs + VWG + tid < nc) fetch(cs + VWG + tid);
+    }
+    // the rows' first entries are fetched only now, so that they hold no
+    // registers while the cells are evaluated
+    int cur[VKR], end[VKR];
+    uint32_t pe[VKR][VPRE];
+    double acc[VKR];
+#pragma unroll
+    for (int k = 0; k < VKR; ++k) {
+        const int r = r0 + tid + VWG * k;
+        cur[k] = r < r1 ? a.inc_ptr[r] : 0;
+        end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
+        acc[k] = 0.0;
+#pragma unroll
+        for (int m = 0; m < VPRE; ++m) pe[k][m] = cur[k] + m < end[k] ? a.ent[cur[k] + m] : 0u;
     }
     lds_barrier();
     // every row sums its cells' local values in ascending cell order

@@ -181,6 +181,56 @@ def split_groups(entries, cost, G):
     return [sorted(g) for g in groups], load
 
 
+def emit_act_t(d, n, NM, stiff, mass):
+    """y += A x with the stiffness terms grouped by metric pair.
+
+    A_ij = sum_mn G[mn] s_ij,mn + madet Mref_ij with s_ij,mn = sum_k kc[k]
+    W[k][mn][i][j], kc[k] = cstiff kappa_k and G[mn] = |det J| grad l_m .
+    grad l_n: only the d+1 values kc and the metric are live instead of the
+    (d+1) x NM products P.  Where at most d+1 distinct coefficient vectors
+    W[.][mn][i][j] occur (P1: one, the mean of kappa) their dot products
+    with kc are formed once per cell.
+    """
+    nv = d + 1
+    groups = {}
+    for e, terms in stiff.items():
+        byt = {}
+        for (kk, t, w) in terms:
+            byt.setdefault(t, {})[kk] = w
+        groups[e] = [(t, tuple(byt[t].get(kk, Fraction(0)) for kk in range(nv))) for t in sorted(byt)]
+    vecs = sorted({v for g in groups.values() for (_, v) in g})
+    shared = len(vecs) <= nv
+
+    def dot(v):
+        expr = None
+        for kk, w in enumerate(v):
+            if w == 0:
+                continue
+            expr = f"{hexlit(w)} * kc[{kk}]" if expr is None else f"__builtin_fma({hexlit(w)}, kc[{kk}], {expr})"
+        return expr
+
+    out = ["  // y += A x for one cell, stiffness terms grouped by metric pair (kc = cstiff kappa, G = metric)",
+           "  __device__ __forceinline__ static void act_t(const double* __restrict__ kc, const double* __restrict__ G, double madet, const double* __restrict__ x, double* __restrict__ y) {"]
+    if shared:
+        for q, v in enumerate(vecs):
+            out.append(f"    const double q{q} = {dot(v)};")
+    for i in range(n):
+        for j in range(i, n):
+            expr = None
+            mw = mass[(i, j)]
+            if mw != 0:
+                expr = f"{hexlit(mw)} * madet"
+            for (t, v) in groups[(i, j)]:
+                s = f"q{vecs.index(v)}" if shared else f"({dot(v)})"
+                expr = f"G[{t}] * {s}" if expr is None else f"__builtin_fma(G[{t}], {s}, {expr})"
+            out.append("    {")
+            out.append(f"      const double e = {expr if expr else '0.0'};")
+            out.append(f"      y[{i}] = __builtin_fma(e, x[{j}], y[{i}]);" + (f" y[{j}] = __builtin_fma(e, x[{i}], y[{j}]);" if i != j else ""))
+            out.append("    }")
+    out.append("  }")
+    return out
+
+
 def emit(d, k, G):
     n, pairs, stiff, mass, src = tables(d, k)
     nv = d + 1
@@ -228,6 +278,7 @@ def emit(d, k, G):
             out.append(f"      y[{i}] = __builtin_fma(e, x[{j}], y[{i}]);" + (f" y[{j}] = __builtin_fma(e, x[{i}], y[{j}]);" if i != j else ""))
             out.append("    }")
     out.append("  }")
+    out.extend(emit_act_t(d, n, NM, stiff, mass))
     out.append("  // b_i = adet * sum_k f_k int l_k phi_i")
     out.append("  __device__ __forceinline__ static void vec(const double* __restrict__ f, double adet, double* __restrict__ b) {")
     for i in range(n):
