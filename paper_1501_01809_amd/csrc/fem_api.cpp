@@ -428,7 +428,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     std::vector<int32_t> colmark(is_mat ? nrows : 0, -1);
     std::vector<int32_t> slot_ptr, lane_ptr, lane_slots, cursor;
     std::vector<uint16_t> con_idx, con_q;   // per contribution: LDS index of the entry, chunk
-    std::vector<int32_t> weight, order, bucket, lane_of, load;
+    std::vector<int32_t> weight, home, order, tmp_order, bucket, qstart, lane_of, load;
     std::vector<std::vector<int32_t>> by_load;
     std::vector<std::vector<uint16_t>> lane_ent(MW);
     int64_t nchunks = 0;
@@ -479,39 +479,73 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
             }
             for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = -1;
         }
-        // weights: per chunk touched, one open plus the entries
-        weight.assign(ns, 0);
+        // Each value's stream entries per chunk it touches are one open plus
+        // its entries there; its home is the chunk where it has the most.
+        // A (chunk, wave) stream is as long as its longest lane, so the loads
+        // are balanced chunk by chunk: the values homed in chunk q, heaviest
+        // first, go to the lane with the least load in chunk q so far
+        // (longest-processing-time; the load already includes what values
+        // homed in earlier chunks put there).  Loads only grow, so a bucket
+        // queue keyed by load finds that lane; lanes enter in wave-interleaved
+        // order so ties spread over the waves.  With one chunk this is plain
+        // LPT on the value weights.
+        home.resize(ns);
+        weight.resize(ns);
         int wmax = 0;
         for (int t = 0; t < ns; ++t) {
-            int w = slot_ptr[t + 1] - slot_ptr[t];
-            for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1]; ++k)
-                w += (k == slot_ptr[t] || con_q[k] != con_q[k - 1]);
-            weight[t] = w;
-            wmax = std::max(wmax, w);
+            int best = 0, hq = 0;
+            for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
+                int32_t k1 = k;
+                while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
+                if (k1 - k + 1 > best) { best = k1 - k + 1; hq = con_q[k]; }
+                k = k1;
+            }
+            home[t] = hq;
+            weight[t] = best;
+            wmax = std::max(wmax, best);
         }
+        // order: by home chunk, then heaviest first (two stable counting sorts)
         bucket.assign(wmax + 2, 0);
         for (int t = 0; t < ns; ++t) ++bucket[wmax - weight[t] + 1];
         for (int w = 0; w <= wmax; ++w) bucket[w + 1] += bucket[w];
+        tmp_order.resize(ns);
+        for (int t = 0; t < ns; ++t) tmp_order[bucket[wmax - weight[t]]++] = t;
+        qstart.assign(nq + 1, 0);
+        for (int t = 0; t < ns; ++t) ++qstart[home[t] + 1];
+        for (int q = 0; q < nq; ++q) qstart[q + 1] += qstart[q];
         order.resize(ns);
-        for (int t = 0; t < ns; ++t) order[bucket[wmax - weight[t]]++] = t;
-        // longest-processing-time: each value, heaviest first, goes to the
-        // least-loaded lane (loads only grow, so a bucket queue keyed by load
-        // finds it); lanes enter in wave-interleaved order so ties spread
-        // over the waves
+        {
+            std::vector<int32_t> fill(qstart.begin(), qstart.end() - 1);
+            for (int p = 0; p < ns; ++p) order[fill[home[tmp_order[p]]]++] = tmp_order[p];
+        }
         lane_of.resize(ns);
-        load.assign(MW, 0);
-        for (auto &v : by_load) v.clear();
-        if (by_load.empty()) by_load.resize(1);
-        for (int l = MW - 1; l >= 0; --l) by_load[0].push_back((l % NW) * 64 + l / NW);
-        for (int p = 0, m = 0; p < ns; ++p) {
-            while (by_load[m].empty()) ++m;
-            const int l = by_load[m].back();
-            by_load[m].pop_back();
-            const int t = order[p];
-            lane_of[t] = l;
-            load[l] += weight[t];
-            if ((int)by_load.size() <= load[l]) by_load.resize(load[l] + 1);
-            by_load[load[l]].push_back(l);
+        load.assign((size_t)nq * MW, 0);
+        for (int q = 0; q < nq; ++q) {
+            if (qstart[q] == qstart[q + 1]) continue;
+            int32_t *lq = load.data() + (size_t)q * MW;
+            int kmax = 0;
+            for (int l = 0; l < MW; ++l) kmax = std::max(kmax, lq[l]);
+            for (auto &v : by_load) v.clear();
+            if ((int)by_load.size() <= kmax) by_load.resize(kmax + 1);
+            for (int i = MW - 1; i >= 0; --i) {
+                const int l = (i % NW) * 64 + i / NW;
+                by_load[lq[l]].push_back(l);
+            }
+            for (int p = qstart[q], m = 0; p < qstart[q + 1]; ++p) {
+                while (by_load[m].empty()) ++m;
+                const int l = by_load[m].back();
+                by_load[m].pop_back();
+                const int t = order[p];
+                lane_of[t] = l;
+                for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
+                    int32_t k1 = k;
+                    while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
+                    load[(size_t)con_q[k] * MW + l] += k1 - k + 1;
+                    k = k1;
+                }
+                if ((int)by_load.size() <= lq[l]) by_load.resize(lq[l] + 1);
+                by_load[lq[l]].push_back(l);
+            }
         }
         lane_ptr.assign(MW + 1, 0);
         for (int t = 0; t < ns; ++t) ++lane_ptr[lane_of[t] + 1];

@@ -104,14 +104,17 @@ __device__ __forceinline__ T ldc(const T *p)
 // LDS).  A chunk of CCH cells is computed LPC lanes per cell (each lane
 // evaluates NG/LPC entry groups of the element tensor); LDS holds, in
 // doubles, [0, SCAP) the block's Mat values, [SCAP, SCAP + CCH*NE) the
-// chunk's packed element tensors and one -0.0 at ZIDX.
+// chunk's packed element tensors and one -0.0 at ZIDX.  A block holds at
+// most MCH chunks of cells (its values stay in LDS while the chunks pass
+// through); MCH was measured per case: more chunks lower the redundancy
+// until the value area, not the cells, bounds the block.
 constexpr int MWG = 512;
 constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 1; };
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4; };
 template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16; };
 template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1, MCH = 1; };
-template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 1; };
+template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 2; };
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4; };
 template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8; };
 
@@ -375,19 +378,18 @@ __device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, in
 // Persistent: one workgroup per CU walks a contiguous range of row blocks
 // (the workgroups of one XCD, launch index mod 8, take one contiguous eighth
 // of the blocks, so neighbouring blocks share that XCD's L2).  Software
-// pipeline over the blocks: the headers of block b+2, the stream offsets,
-// first-chunk stream batches, vertex ids and coordinates of block b+1 are
-// all in flight while block b computes and walks its stream.  Per block:
-//   first chunk: issue the next block's vertex ids; compute the element
-//     tensors into LDS (cell data gathered during the previous block);
-//     barrier; (last chunk) issue the next block's coordinates; walk the
-//     stream; (last chunk) issue the next block's first stream batches;
-//     barrier;
-//   further chunks (rare: a row meeting more cells than a chunk holds): the
-//     same with the chunk's data gathered on the spot;
-//   write the block's Mat values out (one contiguous, coalesced range) and
-//   reset the value area to -0.0, the identity of the sums, for the next
-//   block (each lane touches the same LDS values in both loops).
+// pipeline over the units (block, chunk): while one unit computes and walks
+// its stream, the next unit's vertex ids, coordinates and first stream
+// batches are in flight (the next chunk of the block, or the first chunk of
+// the next block), and the header of block b+2 is loaded.  Per unit:
+//   issue the next unit's vertex ids; compute the element tensors into LDS
+//   (cell data gathered during the previous unit); barrier; issue the next
+//   unit's coordinates; walk the stream; issue the next unit's first stream
+//   batches; barrier.
+// After a block's last unit: write its Mat values out (one contiguous,
+// coalesced range) and reset the value area to -0.0, the identity of the
+// sums, for the next block (each lane touches the same LDS values in both
+// loops).
 // The common path has no branch around a global load, and every prefetched
 // register is consumed before a younger load is waited for, so the
 // compiler's waits stay exact and never drain the prefetches.
@@ -435,67 +437,54 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
     for (int b = bb; b < be; ++b) {
         const bool more = b + 1 < be;
         const MatBlk hnn = b + 2 < be ? mat_blk(a, b + 2) : hn;
-        int nbn = 0;
-        const u32x4 *__restrict__ psn = ps;
-        if (more && hn.nq() > 0) chunk_stream(a, hn, 0, wave, lane, nbn, psn);
-        // prefetch for the next block (uniform; lanes past its cells load a
-        // duplicate of its last cell, unused)
-        const bool pf = more && hn.nc() > 0;
-        const int vnext = hn.c0() + (lcc < hn.nc() ? lcc : hn.nc() - 1);
-        if (h.nq() > 0) {
-            if (pf) vn.load(a.bverts, vnext);
-            if (has_item && lcc < h.nc()) {
+        // One unit per chunk.  While chunk q of block b computes and walks
+        // its stream, the next unit's data are in flight: chunk q+1 of this
+        // block, or after the last chunk the first chunk of the next block.
+        for (int q = 0; q < h.nq(); ++q) {
+            const bool last = q + 1 == h.nq();
+            const MatBlk hx = last ? hn : h;
+            const int qx = last ? 0 : q + 1;
+            const bool sx = last ? more && hn.nq() > 0 : true;   // next unit has a stream
+            const bool cx = last ? more && hn.nc() > 0 : true;   // next unit has cells
+            int nbx = 0;
+            const u32x4 *__restrict__ psx = ps;
+            if (sx) chunk_stream(a, hx, qx, wave, lane, nbx, psx);
+            // uniform prefetch; lanes past the next chunk's cells load a
+            // duplicate of the block's last cell, unused
+            const int lcx = qx * CCH + lcc;
+            if (cx) vn.load(a.bverts, hx.c0() + (lcx < hx.nc() ? lcx : hx.nc() - 1));
+            if (has_item && q * CCH + lcc < h.nc()) {
                 double P[NP], madet;
                 tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
                 mat_part<T, LPC>(part, P, madet, E);
             }
             lds_barrier();
             hold_stream(sv);
-            if (h.nq() == 1 && pf) {
+            if (cx) {
                 int32_t v[D + 1];
                 vn.hold();
                 vn.get(v);
                 issue_coords<D>(v, a.coords, a.coeff, cin);
             }
             pull_stream<L::SCAP, L::ZIDX>(sv, ps, nb, lds);
-            if (h.nq() == 1 && more && hn.nq() > 0) load_stream(sv, psn, nbn);
+            if (sx) {
+                load_stream(sv, psx, nbx);
+                nb = nbx;
+                ps = psx;
+            }
             lds_barrier();
         }
-        for (int q = 1; q < h.nq(); ++q) {
-            const int lc = q * CCH + lcc;
-            if (has_item && lc < h.nc()) {
+        if (h.nq() == 0 && more) {
+            // a block without cells: start the next block's first chunk here
+            if (hn.nc() > 0) {
                 int32_t v[D + 1];
-                CellIn<D> cq;
-                issue_verts<D>(a.bverts, h.c0() + lc, v);
-                issue_coords<D>(v, a.coords, a.coeff, cq);
-                double P[NP], madet;
-                tensor_inputs<D>(cq, a.cstiff, a.cmass, P, &madet);
-                mat_part<T, LPC>(part, P, madet, E);
-            }
-            int nbq;
-            const u32x4 *__restrict__ psq;
-            chunk_stream(a, h, q, wave, lane, nbq, psq);
-            u32x4 svq[NBMAX];
-            load_stream(svq, psq, nbq);
-            lds_barrier();
-            hold_stream(svq);
-            if (q == h.nq() - 1 && pf) {
-                int32_t v[D + 1];
-                vn.hold();
-                vn.get(v);
+                issue_verts<D>(a.bverts, hn.c0() + (lcc < hn.nc() ? lcc : hn.nc() - 1), v);
                 issue_coords<D>(v, a.coords, a.coeff, cin);
             }
-            pull_stream<L::SCAP, L::ZIDX>(svq, psq, nbq, lds);
-            if (q == h.nq() - 1 && more && hn.nq() > 0) load_stream(sv, psn, nbn);
-            lds_barrier();
-        }
-        if (h.nq() == 0) {
-            if (pf) {
-                int32_t v[D + 1];
-                issue_verts<D>(a.bverts, vnext, v);
-                issue_coords<D>(v, a.coords, a.coeff, cin);
+            if (hn.nq() > 0) {
+                chunk_stream(a, hn, 0, wave, lane, nb, ps);
+                load_stream(sv, ps, nb);
             }
-            if (more && hn.nq() > 0) load_stream(sv, psn, nbn);
         }
         // write-out: CO values per lane in flight at once
         double *__restrict__ out = a.out + h.s0();
@@ -516,8 +505,6 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
         for (int s = tid; s < hn.ns(); s += MWG) lds[s] = -0.0;
         h = hn;
         hn = hnn;
-        nb = nbn;
-        ps = psn;
     }
 }
 

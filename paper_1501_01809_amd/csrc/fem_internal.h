@@ -22,9 +22,9 @@ struct fem_ctx {
 //  * Dat/action plans: every row's incident entries (inc_ptr / ent, ascending
 //    cell) name a cell of the block list (local index) and the row's local
 //    index in that cell.
-//  * Mat plans: the block's cells are processed in chunks of at most Limits::cell_cap
-//    cells whose packed element tensors sit in LDS together with the block's
-//    Mat values.  Every lane of the workgroup owns a set of the block's Mat
+//  * Mat plans: the block's cells (at most Limits::cell_cap) are processed in
+//    chunks of at most Limits::chunk_cells cells whose packed element tensors
+//    sit in LDS together with the block's Mat values.  Every lane of the workgroup owns a set of the block's Mat
 //    values and walks its own stream of 16-bit LDS indices: an index below
 //    the value area's size opens that value (the running sum restarts from
 //    the value held there), any other index adds one element-tensor entry
