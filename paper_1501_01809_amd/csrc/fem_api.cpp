@@ -569,13 +569,13 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
                 }
             }
             for (int w = 0; w < NW; ++w) {
-                wq.push_back((int32_t)(stream.size() / 8));
+                wq.push_back((int32_t)(stream.size() / femk::MAT_BATCH));
                 size_t len = 0;
                 for (int l = 64 * w; l < 64 * w + 64; ++l) len = std::max(len, lane_ent[l].size());
-                const size_t nb = std::max<size_t>(1, (len + 7) / 8);   // the kernel loads one batch at least
+                const size_t nb = std::max<size_t>(1, (len + femk::MAT_BATCH - 1) / femk::MAT_BATCH);   // one batch at least
                 for (size_t i = 0; i < nb; ++i)
                     for (int l = 64 * w; l < 64 * w + 64; ++l)
-                        for (size_t j = 8 * i; j < 8 * i + 8; ++j)
+                        for (size_t j = femk::MAT_BATCH * i; j < femk::MAT_BATCH * (i + 1); ++j)
                             stream.push_back(j < lane_ent[l].size() ? lane_ent[l][j] : (uint16_t)ZIDX);
             }
         }
@@ -629,8 +629,8 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     if (rows > 0) close_block(nrows);
     if (missing) return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
     if (is_mat) {
-        wq.push_back((int32_t)(stream.size() / 8));
-        if (stream.size() / 8 > (size_t)INT32_MAX)
+        wq.push_back((int32_t)(stream.size() / femk::MAT_BATCH));
+        if (stream.size() / femk::MAT_BATCH > (size_t)INT32_MAX)
             return fail(ctx, FEM_E_OVERFLOW, "plan_create: Mat streams exceed 2^31 batches");
     }
 
@@ -737,10 +737,11 @@ static fem_status check_nodal(fem_ctx *ctx, const fem_args *args, int need)
     return FEM_OK;
 }
 
-static femk::AsmArgs base_args(const fem_plan *plan, const fem_args *args)
+static femk::AsmArgs base_args(const fem_ctx *ctx, const fem_plan *plan, const fem_args *args)
 {
     femk::AsmArgs a{};
     a.plan = plan;
+    a.num_cus = ctx->num_cus;
     a.cell_vertex = args->cell_vertex->values;
     a.coords = args->coords->data;
     a.cell_node = args->cell_node->values;
@@ -764,7 +765,7 @@ fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const f
     if (A->sp->row_ptr != plan->row_ptr || A->sp->nnz != plan->nnz)
         return fail(ctx, FEM_E_ARG, "assemble_mat: Mat sparsity differs from the plan's");
     if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "a Mat accepts only WRITE or INC");
-    femk::AsmArgs a = base_args(plan, args);
+    femk::AsmArgs a = base_args(ctx, plan, args);
     form_coeffs(form->kind, &a.cstiff, &a.cmass);
     a.coeff = need_k ? args->coeff[0]->data : args->coords->data;   // unread when cstiff == 0
     a.row_ptr = A->sp->row_ptr;
@@ -791,7 +792,7 @@ fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const f
         if (!dat_ok(b, args->cell_node->to, 1))
             return fail(ctx, FEM_E_ARG, "assemble_vec: b must be a Dat on the nodes");
         if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
-        femk::AsmArgs a = base_args(plan, args);
+        femk::AsmArgs a = base_args(ctx, plan, args);
         a.x = args->coeff[0]->data;
         a.coeff = args->coeff[1]->data;
         a.aux = args->coeff[2]->data;
@@ -805,7 +806,7 @@ fem_status fem_par_loop_assemble_vec(fem_ctx *ctx, const fem_plan *plan, const f
     if ((st = check_plan(ctx, plan, form, args, false)) != FEM_OK) return st;
     if (!dat_ok(b, args->cell_node->to, 1)) return fail(ctx, FEM_E_ARG, "assemble_vec: b must be a Dat on the nodes");
     if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
-    femk::AsmArgs a = base_args(plan, args);
+    femk::AsmArgs a = base_args(ctx, plan, args);
     a.coeff = args->coeff[0]->data;
     a.out = b->data;
     a.inc = acc == FEM_INC;
@@ -831,7 +832,7 @@ fem_status fem_apply_action(fem_ctx *ctx, const fem_plan *plan, const fem_form *
         return fail(ctx, FEM_E_ARG, "apply_action: x and y must be Dats on the nodes");
     if (x->data == y->data && x->set->size > 0) return fail(ctx, FEM_E_ARG, "apply_action: x and y alias");
     if (acc != FEM_WRITE && acc != FEM_INC) return fail(ctx, FEM_E_ARG, "output access must be WRITE or INC");
-    femk::AsmArgs a = base_args(plan, args);
+    femk::AsmArgs a = base_args(ctx, plan, args);
     form_coeffs(form->kind, &a.cstiff, &a.cmass);
     a.coeff = need_k ? args->coeff[0]->data : args->coords->data;
     a.x = x->data;
@@ -864,7 +865,7 @@ fem_status fem_par_loop_assemble_adjoint(fem_ctx *ctx, const fem_plan *plan, con
             return fail(ctx, FEM_E_ARG, "assemble_adjoint: an output aliases an input");
     if (g_u && g_kappa && g_u->data == g_kappa->data && nodes->size > 0)
         return fail(ctx, FEM_E_ARG, "assemble_adjoint: g_u and g_kappa alias");
-    femk::AsmArgs a = base_args(plan, args);
+    femk::AsmArgs a = base_args(ctx, plan, args);
     a.x = args->coeff[0]->data;
     a.coeff = args->coeff[1]->data;
     a.aux = lambda->data;
@@ -897,7 +898,7 @@ fem_status fem_par_loop_reduce(fem_ctx *ctx, const fem_plan *plan, const fem_for
         return fail(ctx, FEM_E_ARG, "reduce: a Global accepts SUM, MIN or MAX");
     if (energy && !dat_ok(x, args->cell_node->to, 1))
         return fail(ctx, FEM_E_ARG, "reduce: the energy needs x, a Dat on the nodes");
-    femk::AsmArgs a = base_args(plan, args);
+    femk::AsmArgs a = base_args(ctx, plan, args);
     form_coeffs(energy ? form->kind : FEM_MASS, &a.cstiff, &a.cmass);
     a.coeff = need_k ? args->coeff[0]->data : args->coords->data;   // unread when cstiff == 0
     a.x = energy ? x->data : nullptr;
@@ -931,7 +932,7 @@ fem_status fem_par_loop_assemble_mixed(fem_ctx *ctx, const fem_plan *plan, const
     for (int32_t q = 0; q < nfields * nfields; ++q) {
         const fem_block &bk = blocks[q];
         if (!mats[q].values) continue;
-        femk::AsmArgs a = base_args(plan, args);
+        femk::AsmArgs a = base_args(ctx, plan, args);
         form_coeffs(bk.kind, &a.cstiff, &a.cmass);
         a.cstiff *= bk.scale;
         a.cmass *= bk.scale;

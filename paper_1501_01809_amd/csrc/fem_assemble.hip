@@ -29,6 +29,11 @@ namespace {
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+template <int W> struct BatchOf;
+template <> struct BatchOf<8> { typedef u32x4 T; };
+template <> struct BatchOf<4> { typedef u32x2 T; };
+typedef BatchOf<MAT_BATCH>::T Batch;   // one lane's batch of Mat stream indices
 
 // Everything a kernel reads, by value: device pointers and scalars only.
 struct KArgs {
@@ -41,7 +46,7 @@ struct KArgs {
     const int32_t *__restrict__ blk_hdr;
     const int32_t *__restrict__ blk_w;
     const int32_t *__restrict__ wq;
-    const uint32_t *__restrict__ pstream;   // 16-byte batches
+    const uint32_t *__restrict__ pstream;   // batches of MAT_BATCH 16-bit indices
     const int64_t *__restrict__ row_ptr;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
@@ -109,7 +114,7 @@ __device__ __forceinline__ T ldc(const T *p)
 // through); MCH was measured per case: more chunks lower the redundancy
 // until the value area, not the cells, bounds the block.
 constexpr int MWG = 512;
-constexpr int NBMAX = 8;      // stream batches (8 indices each) held in registers
+constexpr int NBMAX = 64 / MAT_BATCH;   // stream batches held in registers (64 indices)
 template <int D, int K> struct MatCfg;
 template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4; };
 template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16; };
@@ -273,27 +278,28 @@ __device__ __forceinline__ void mat_part(int part, const double *P, double madet
     }
 }
 
-// One batch of 8 stream indices of a lane.  The lane keeps the running sum
-// of the Mat value it has open in registers (acc, its LDS byte address in
-// cur).  Index i < SCAP opens Mat value i: the open value is written back
-// and the running sum restarts from what LDS holds at i (-0.0 the first
-// time, a partial sum from an earlier chunk otherwise); any other index adds
-// the LDS double it names.  All 8 loads are issued first: an opened value is
-// never written earlier in the same batch (a lane opens each value once per
-// chunk, and writes only values it has open).
+// One batch of MAT_BATCH stream indices of a lane.  The lane keeps the
+// running sum of the Mat value it has open in registers (acc, its LDS byte
+// address in cur).  Index i < SCAP opens Mat value i: the open value is
+// written back and the running sum restarts from what LDS holds at i (-0.0
+// the first time, a partial sum from an earlier chunk otherwise); any other
+// index adds the LDS double it names.  All loads of the batch are issued
+// first: an opened value is never written earlier in the same batch (a lane
+// opens each value once per chunk, and writes only values it has open).
 template <int SCAP>
-__device__ __forceinline__ void pull_batch(const u32x4 w, char *lds, uint32_t &cur, double &acc)
+__device__ __forceinline__ void pull_batch(const Batch w, char *lds, uint32_t &cur, double &acc)
 {
-    const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
-    uint32_t ad[8];
-    double v[8];
+    constexpr int NI = MAT_BATCH;
+    uint32_t ad[NI];
+    double v[NI];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        ad[j] = ((j & 1) ? (wd[j >> 1] >> 16) : (wd[j >> 1] & 0xffffu)) << 3;   // byte address
+    for (int j = 0; j < NI; ++j) {
+        const uint32_t wd = w[j >> 1];
+        ad[j] = ((j & 1) ? (wd >> 16) : (wd & 0xffffu)) << 3;   // byte address
         v[j] = *reinterpret_cast<const double *>(lds + ad[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NI; ++j) {
         const bool open = ad[j] < (uint32_t)SCAP * 8u;
         const double sum = acc + v[j];
         if (open) *reinterpret_cast<double *>(lds + cur) = acc;
@@ -337,7 +343,7 @@ __device__ __forceinline__ void hold(T &x)
 // longer streams load the rest one batch at a time.  Ends by writing back
 // the value left open.
 template <int SCAP, int ZIDX>
-__device__ __forceinline__ void pull_stream(u32x4 (&sv)[NBMAX], const u32x4 *__restrict__ ps, int nb,
+__device__ __forceinline__ void pull_stream(Batch (&sv)[NBMAX], const Batch *__restrict__ ps, int nb,
                                             double *lds)
 {
     char *lb = reinterpret_cast<char *>(lds);
@@ -354,13 +360,13 @@ __device__ __forceinline__ void pull_stream(u32x4 (&sv)[NBMAX], const u32x4 *__r
 // the chunk's element tensors were computed, so they have long arrived).
 // Done before any younger prefetch is issued, the stream walk then waits for
 // nothing (waits count loads in issue order).
-__device__ __forceinline__ void hold_stream(u32x4 (&sv)[NBMAX])
+__device__ __forceinline__ void hold_stream(Batch (&sv)[NBMAX])
 {
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) asm volatile("" : "+v"(sv[i]));
 }
 
-__device__ __forceinline__ void load_stream(u32x4 (&sv)[NBMAX], const u32x4 *__restrict__ ps, int nb)
+__device__ __forceinline__ void load_stream(Batch (&sv)[NBMAX], const Batch *__restrict__ ps, int nb)
 {
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) sv[i] = ps[(int64_t)(i < nb ? i : nb - 1) * 64];
@@ -368,11 +374,11 @@ __device__ __forceinline__ void load_stream(u32x4 (&sv)[NBMAX], const u32x4 *__r
 
 // Stream of chunk q of a block, for this wave.
 __device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, int q, int wave, int lane, int &nb,
-                                             const u32x4 *__restrict__ &ps)
+                                             const Batch *__restrict__ &ps)
 {
     const int st = ldc(a.wq + h.w0() + 8 * q + wave);
     nb = (ldc(a.wq + h.w0() + 8 * q + wave + 1) - st) >> 6;
-    ps = reinterpret_cast<const u32x4 *>(a.pstream) + st + lane;
+    ps = reinterpret_cast<const Batch *>(a.pstream) + st + lane;
 }
 
 // Persistent: one workgroup per CU walks a contiguous range of row blocks
@@ -418,8 +424,8 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
     MatBlk h = mat_blk(a, bb);
     MatBlk hn = bb + 1 < be ? mat_blk(a, bb + 1) : h;
     int nb = 0;
-    const u32x4 *__restrict__ ps = nullptr;
-    u32x4 sv[NBMAX];             // first-chunk stream batches of the current block
+    const Batch *__restrict__ ps = nullptr;
+    Batch sv[NBMAX];             // first stream batches of the current unit
     CellIn<D> cin;               // first-chunk cell data of the current block
     VIds<D> vn;                  // vertex ids of the next block's first-chunk cell
     if (h.nq() > 0) {
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
             const bool sx = last ? more && hn.nq() > 0 : true;   // next unit has a stream
             const bool cx = last ? more && hn.nc() > 0 : true;   // next unit has cells
             int nbx = 0;
-            const u32x4 *__restrict__ psx = ps;
+            const Batch *__restrict__ psx = ps;
             if (sx) chunk_stream(a, hx, qx, wave, lane, nbx, psx);
             // uniform prefetch; lanes past the next chunk's cells load a
             // duplicate of the block's last cell, unused

@@ -31,10 +31,10 @@ struct fem_ctx {
 //    (or -0.0, the identity, for padding).  A value's entries come in
 //    ascending cell id, the same order in every block, so the sums are
 //    reproducible and an assembled symmetric form is bitwise symmetric.
-//    The stream of (chunk q, wave w) of a block starts at uint4 index
+//    The stream of (chunk q, wave w) of a block starts at batch index
 //    wq[blk_w[b] + 8q + w] and ends where the next one starts; inside it,
-//    batch i of lane l is the uint4 at start + 64 i + l (8 indices, the
-//    first in the low half of .x).
+//    batch i of lane l is the batch at start + 64 i + l (femk::MAT_BATCH
+//    indices, two per 32-bit word, the first in the low half).
 struct fem_plan {
     int is_mat = 0;
     int dim = 0, degree = 0, nloc = 0;
@@ -72,7 +72,7 @@ struct fem_plan {
     uint16_t *ent = nullptr;      // Dat plans: (local cell << lbits) | local index
     int32_t *blk_hdr = nullptr;   // Mat plans: [nblk][8] block header (layout in fem_assemble.hip)
     int32_t *blk_w = nullptr;     // Mat plans: [nblk+1] first (chunk, wave) stream of each block
-    int32_t *wq = nullptr;        // Mat plans: [streams+1] first uint4 of each (chunk, wave) stream
+    int32_t *wq = nullptr;        // Mat plans: [streams+1] first batch of each (chunk, wave) stream
     uint16_t *pstream = nullptr;  // Mat plans: the streams
     // identity of what the plan was built for
     const int32_t *cell_node = nullptr;
@@ -80,6 +80,16 @@ struct fem_plan {
 };
 
 namespace femk {
+
+// 16-bit indices per Mat stream batch (one 16- or 8-byte load per lane).
+// Batches of 4 cut the rounding padding (P2 tetrahedra: plan 702 -> 661 MB)
+// but measured slower everywhere (P2 tetrahedra 503 -> 535 us): twice the
+// load instructions and half the LDS reads in flight per batch.
+#ifndef FEM_MAT_BATCH
+#define FEM_MAT_BATCH 8
+#endif
+constexpr int MAT_BATCH = FEM_MAT_BATCH;
+static_assert(MAT_BATCH == 4 || MAT_BATCH == 8, "Mat stream batch width");
 
 // ---- incidence and sparsity (fem_sparsity.hip) ----
 hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hipStream_t s);
