@@ -273,7 +273,8 @@ def bench_precision(ctx, steps: int, warmup: int, seed: int, n: int = 48):
     return out
 
 
-def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: int = 8):
+def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: int = 4,
+                  max_wait_ms: float = 100.0):
     """The serving workload: a stream of `nreq` requests with Poisson arrivals
     at rate load / s, s the mean isolated service time of the mix.  Each
     request is an assembly (CSR matrix + right-hand side) or a matrix-free
@@ -281,7 +282,9 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
     (unit-square triangles, n in 16..512; Kuhn cubes, n in 8..64), size and
     Lagrange degree 1..3; jittered meshes, fields U[0.5, 1.5].  The same
     arrival sequence is served with `slots` slots and with one slot (no
-    overlap).  Latency = completion seen by the poll loop minus arrival."""
+    overlap), and with `slots` slots admitting the smallest queued request
+    first (a queue head that has waited max_wait_ms goes first).  Latency =
+    completion seen by the poll loop minus arrival."""
     import torch
     import fem_inputs as fi
     from paper_1501_01809_amd import fem as F
@@ -392,8 +395,13 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
                            for sp_ in specs}}
     log(f"serving: {len(specs)} models resident ({resident / 1e9:.1f} GB), setup {setup_ms / 1e3:.1f} s, "
         f"mean isolated service {sbar * 1e3:.3f} ms; {slots} slots")
-    for name, ns, share in (("batched", slots, True), ("batched_full_grid", slots, False), ("one_slot", 1, False)):
+    out["shortest_max_wait_ms"] = max_wait_ms
+    for name, ns, share, order in (("batched", slots, True, F.FEM_SERVE_FIFO),
+                                   ("batched_shortest", slots, True, F.FEM_SERVE_SHORTEST),
+                                   ("batched_full_grid", slots, False, F.FEM_SERVE_FIFO),
+                                   ("one_slot", 1, False, F.FEM_SERVE_FIFO)):
         srv.configure(ns, share)
+        srv.set_order(order, max_wait_ms * 1e-3)
         out[name] = run(srv)
         log(f"serving: {name} ({ns} slots) p50 {out[name]['p50_ms']:.2f} ms p99 {out[name]['p99_ms']:.2f} ms")
     srv.close()

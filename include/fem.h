@@ -418,7 +418,8 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
  * integral of f v, WRITE) or FEM_REQ_ACTION (y = A x for the caller's x on the
  * model's nodes).  Submitted requests queue in arrival order.
  * fem_server_poll, which never blocks, retires requests whose work has
- * finished and admits the queue head while one of the `slots` is free and the
+ * finished and admits the queue head (or, by fem_server_set_order, the
+ * smallest queued request) while one of the `slots` is free and the
  * request's outputs fit the HBM budget (hbm_budget bytes for resident models
  * plus outputs in flight).  Outputs come from an arena of the budget left
  * after the resident models, allocated at the first admission (so models
@@ -459,6 +460,15 @@ fem_status fem_server_take_completed(fem_server *server, int64_t *ids, int32_t c
  * launches its persistent Mat kernel on half the compute units, so that it
  * does not shut the others out for its whole duration. */
 fem_status fem_server_configure(fem_server *server, int32_t slots, int32_t share_cus);
+/* Which queued request admission takes next.  FEM_SERVE_FIFO (the default):
+ * the queue head.  FEM_SERVE_SHORTEST: the queued request of least estimated
+ * work (cell visits of its plan times the local tensor size, plus the Mat
+ * values of an assembly; ties go to the earlier), except that a head which
+ * has waited max_wait seconds or more (by the poll's `now`) is taken first,
+ * which bounds how long large requests can be passed over.  Results do not
+ * depend on the order.  FEM_E_ARG for an unknown order or max_wait < 0. */
+typedef enum fem_serve_order { FEM_SERVE_FIFO = 0, FEM_SERVE_SHORTEST = 1 } fem_serve_order;
+fem_status fem_server_set_order(fem_server *server, int32_t order, double max_wait);
 /* A resident model's sizes and its sparsity (device pointers owned by the server). */
 fem_status fem_server_model_info(const fem_server *server, int32_t model, int64_t *cells, int64_t *nrows,
                                  int64_t *nnz, const int64_t **row_ptr, const int32_t **col_idx);

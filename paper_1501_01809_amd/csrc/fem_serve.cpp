@@ -8,8 +8,10 @@
 // overheads are what batching amortises, "Experiments").
 //
 // Requests (an assembly: CSR matrix + right-hand side; or an action y = A x)
-// queue in arrival order.  fem_server_poll admits the queue head whenever a
-// slot is free and its output memory fits the budget; an admitted request's
+// queue in arrival order.  fem_server_poll admits the queue head (or, when
+// asked, the queued request of least estimated work, with a bound on how
+// long the head can be passed over) whenever a slot is free and its output
+// memory fits the budget; an admitted request's
 // kernels go onto its slot's stream, so requests that arrive while others
 // are running start at once and overlap on the device with them.  The poll
 // also retires requests whose completion event has fired.  Every kernel is
@@ -72,6 +74,7 @@ struct Request {
     int slot = -1;
     double *values = nullptr, *vec = nullptr;
     int64_t bytes = 0;
+    double work = 0;      // estimated work, for shortest-first admission
     int64_t off_values = -1, off_vec = -1;
 };
 
@@ -125,6 +128,8 @@ struct fem_server {
     int64_t budget = 0, in_use = 0, resident = 0;
     int active = 0;                       // slots admission may use (<= streams.size())
     int share_cus = 1;                    // halve the Mat kernel's grid while others run
+    int order = FEM_SERVE_FIFO;           // which queued request admission takes next
+    double max_wait = 0;                  // FEM_SERVE_SHORTEST: a head waiting this long goes first
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int64_t> slot_req;        // request running on each slot, -1 if free
@@ -134,6 +139,15 @@ struct fem_server {
     std::deque<int64_t> finished;         // completed, not yet handed out by take_completed
     Arena arena;                          // allocated at the first admission
 };
+
+// Work of a request, to order admission: cell visits of its plan times the
+// local tensor size, plus the Mat values an assembly writes.
+static double req_work(const Model &m, int op)
+{
+    const fem_plan &p = op == FEM_REQ_ASSEMBLE ? *m.mplan : *m.vplan;
+    const double nl = p.nloc;
+    return (double)p.cell_visits * nl * nl + (op == FEM_REQ_ASSEMBLE ? (double)m.nnz : 0.0);
+}
 
 static int64_t req_bytes(const Model &m, int op)
 {
@@ -263,6 +277,7 @@ fem_status fem_server_submit(fem_server *s, int32_t model, int32_t op, const dou
         return sfail(ctx, FEM_E_NOMEM, "submit: the request's outputs can never fit the HBM budget");
     Request r;
     r.model = model; r.op = op; r.x = x; r.t_arrival = arrival_time; r.bytes = bytes;
+    r.work = req_work(*s->models[model], op);
     s->reqs.push_back(r);
     s->queue.push_back((int64_t)s->reqs.size() - 1);
     if (req_id) *req_id = (int64_t)s->reqs.size() - 1;
@@ -295,9 +310,16 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
         s->arena.size = size;
         s->arena.free_[0] = size;
     }
-    // admit the queue head while a slot is free and its outputs fit
+    // admit while a slot is free and the next request's outputs fit: the
+    // queue head (FIFO), or the queued request of least estimated work
+    // (ties: the earlier) unless the head has waited max_wait or longer
     while (!s->queue.empty()) {
-        Request &r = s->reqs[s->queue.front()];
+        auto pick = s->queue.begin();
+        if (s->order == FEM_SERVE_SHORTEST && now - s->reqs[*pick].t_arrival < s->max_wait)
+            for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+                if (s->reqs[*it].work < s->reqs[*pick].work) pick = it;
+        const int64_t rid = *pick;
+        Request &r = s->reqs[rid];
         int slot = -1;
         for (int k = 0; k < s->active; ++k)
             if (s->slot_req[k] < 0) { slot = k; break; }
@@ -342,8 +364,8 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
         r.slot = slot;
         r.t_admit = now;
         s->in_use += r.bytes;
-        s->slot_req[slot] = s->queue.front();
-        s->queue.pop_front();
+        s->slot_req[slot] = rid;
+        s->queue.erase(pick);
     }
     int32_t run = 0;
     for (int64_t q : s->slot_req) run += q >= 0;
@@ -403,6 +425,17 @@ fem_status fem_server_configure(fem_server *s, int32_t slots, int32_t share_cus)
         return sfail(s->ctx, FEM_E_ARG, "configure: slots must be 1..%d", (int)s->streams.size());
     s->active = slots;   // running requests on higher slots finish normally
     s->share_cus = share_cus != 0;
+    return FEM_OK;
+}
+
+fem_status fem_server_set_order(fem_server *s, int32_t order, double max_wait)
+{
+    if (!s) return FEM_E_ARG;
+    if (order != FEM_SERVE_FIFO && order != FEM_SERVE_SHORTEST)
+        return sfail(s->ctx, FEM_E_ARG, "set_order: unknown order");
+    if (!(max_wait >= 0)) return sfail(s->ctx, FEM_E_ARG, "set_order: max_wait must be >= 0");
+    s->order = order;
+    s->max_wait = max_wait;
     return FEM_OK;
 }
 

@@ -19,6 +19,7 @@ FEM_OK, FEM_E_ARG, FEM_E_RANGE, FEM_E_OVERFLOW, FEM_E_UNSUPPORTED, FEM_E_NOMEM, 
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_E_ARG", 2: "FEM_E_RANGE", 3: "FEM_E_OVERFLOW",
                 4: "FEM_E_UNSUPPORTED", 5: "FEM_E_NOMEM", 6: "FEM_E_DEVICE"}
 FEM_READ, FEM_WRITE, FEM_INC, FEM_SUM, FEM_MIN, FEM_MAX = 0, 1, 2, 3, 4, 5
+FEM_SERVE_FIFO, FEM_SERVE_SHORTEST = 0, 1
 FEM_TRIANGLE, FEM_TETRAHEDRON = 2, 3
 FEM_FP64, FEM_FP32, FEM_BF16, FEM_FP16 = 0, 1, 2, 3
 FEM_MASS, FEM_LAPLACE, FEM_HELMHOLTZ, FEM_SOURCE, FEM_NL_RESIDUAL, FEM_ELASTICITY = 0, 1, 2, 3, 4, 5
@@ -87,7 +88,7 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
-           "fem_server_configure", "fem_server_take_completed", "fem_par_loop_reduce",
+           "fem_server_configure", "fem_server_set_order", "fem_server_take_completed", "fem_par_loop_reduce",
            "fem_apply_dirichlet", "fem_par_loop_assemble_mixed", "fem_facet_plan_create",
            "fem_par_loop_assemble_facets"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
@@ -143,6 +144,7 @@ def lib():
                                         C.POINTER(C.c_double)]
         L.fem_server_release.argtypes = [P, C.c_int64]
         L.fem_server_configure.argtypes = [P, C.c_int32, C.c_int32]
+        L.fem_server_set_order.argtypes = [P, C.c_int32, C.c_double]
         L.fem_server_take_completed.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
@@ -458,6 +460,11 @@ class Server:
 
     def configure(self, slots: int, share_cus: bool = True):
         self.ctx.check(lib().fem_server_configure(self.h, slots, int(share_cus)))
+
+    def set_order(self, order: int, max_wait: float = 0.0):
+        """FEM_SERVE_FIFO or FEM_SERVE_SHORTEST (least estimated work first; a
+        queue head that has waited max_wait seconds goes first)."""
+        self.ctx.check(lib().fem_server_set_order(self.h, order, max_wait))
 
     def close(self):
         if self.h:

@@ -172,3 +172,34 @@ def test_server_rejections():
         srv.release(rid)
     assert e.value.status == F.FEM_E_ARG
     srv.close()
+
+
+def test_shortest_first_order():
+    """FEM_SERVE_SHORTEST admits the smallest queued request first (unless the
+    head has waited max_wait); results are bitwise those of FIFO admission."""
+    F, ctx, srv, models = _server(1, 8 << 30)
+    big, small = models[5], models[0]      # a P3 tetrahedron assembly, a P1 triangle action
+    with pytest.raises(F.FemError):
+        srv.set_order(7, 0.0)
+    with pytest.raises(F.FemError):
+        srv.set_order(F.FEM_SERVE_SHORTEST, -1.0)
+
+    def run(order, max_wait):
+        srv.set_order(order, max_wait)
+        rb = srv.submit(big["id"], F.FEM_REQ_ASSEMBLE)
+        rs = srv.submit(small["id"], F.FEM_REQ_ACTION, small["g"]["x"])
+        res = _drain(srv, F, [rb, rs], {rb: big, rs: small}, {rb: F.FEM_REQ_ASSEMBLE, rs: F.FEM_REQ_ACTION})
+        return res[rb], res[rs]
+
+    fb, fs = run(F.FEM_SERVE_FIFO, 0.0)
+    assert fb[2] < fs[2], "FIFO admits in arrival order"
+    sb, ss = run(F.FEM_SERVE_SHORTEST, 1e9)
+    assert ss[2] < sb[2], "the smaller request goes first"
+    hb, hs = run(F.FEM_SERVE_SHORTEST, 0.0)
+    assert hb[2] < hs[2], "a head that has waited max_wait goes first"
+    for a, b in ((fb, sb), (fb, hb)):
+        assert np.array_equal(a[0].view(np.uint64), b[0].view(np.uint64))
+        assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
+    for a, b in ((fs, ss), (fs, hs)):
+        assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
+    srv.close()
