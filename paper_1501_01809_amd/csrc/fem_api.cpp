@@ -420,7 +420,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     // Dat plans: packed entries
     std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
     // Mat plans: per-lane LDS index streams (see fem_plan)
-    const int MW = 512, NW = MW / 64;
+    const int MW = is_mat ? lim.lanes : 64, NW = MW / 64;
     const int SCAP = lim.slot_cap, CCH = lim.chunk_cells, NE = lim.ne;
     const int ZIDX = SCAP + CCH * NE;
     std::vector<int32_t> blk_w{0}, wq;
@@ -677,7 +677,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
             hd[2] = (int32_t)(hrp[blk_row0[i + 1]] - s0);
             hd[3] = blk_cptr[i];
             hd[4] = blk_cptr[i + 1] - blk_cptr[i];
-            hd[5] = (blk_w[i + 1] - blk_w[i]) / 8;
+            hd[5] = (blk_w[i + 1] - blk_w[i]) / NW;
             hd[6] = blk_w[i];
         }
         if (e == hipSuccess) e = upload(&p->blk_hdr, hdr, &p->bytes, s);

@@ -113,15 +113,21 @@ __device__ __forceinline__ T ldc(const T *p)
 // most MCH chunks of cells (its values stay in LDS while the chunks pass
 // through); MCH was measured per case: more chunks lower the redundancy
 // until the value area, not the cells, bounds the block.
-constexpr int MWG = 512;
-constexpr int NBMAX = 64 / MAT_BATCH;   // stream batches held in registers (64 indices)
+// WG lanes per workgroup (512 or 1024: 8 or 16 waves on the CU); NB stream
+// batches of a lane held in registers (longer streams load the rest as they
+// go); MT: the element tensors are formed from kc = cstiff kappa and the
+// metric (terms grouped by metric pair) instead of the (d+1) x NM products
+// P, which keeps fewer values live.  All measured per case: MT paid
+// everywhere but on P3 triangles (P2 tetrahedra 510 -> 463 us); 1024 lanes
+// paid on triangles of degree 2 and 3 (16 waves hide more latency) and lost
+// on tetrahedra, whose shorter per-lane streams pad more.
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4; };
-template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16; };
-template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 1, MCH = 1; };
-template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 2; };
-template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4; };
-template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8; };
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
+template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 2, MCH = 1, WG = 1024, NB = 4; static constexpr bool MT = true; };
+template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 2, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
+template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4, WG = 1024, NB = 4; static constexpr bool MT = false; };
+template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 
 // Dat and action kernels: workgroups of VWG lanes, KR rows per lane; the
 // per-cell local vectors of the whole block live in LDS (VLDS doubles, two
@@ -278,6 +284,48 @@ __device__ __forceinline__ void mat_part(int part, const double *P, double madet
     }
 }
 
+// The same entry groups from kc and the metric.
+template <class T, int LPC>
+__device__ __forceinline__ void mat_part_t(int part, const double *kc, const double *G, double madet, double *E)
+{
+    if constexpr (T::NG == 1) {
+        T::mat_group_t0(kc, G, madet, E);
+    } else if constexpr (LPC == 1) {
+        T::mat_group_t0(kc, G, madet, E); T::mat_group_t1(kc, G, madet, E);
+        T::mat_group_t2(kc, G, madet, E); T::mat_group_t3(kc, G, madet, E);
+    } else if constexpr (LPC == 2) {
+        if (part == 0) { T::mat_group_t0(kc, G, madet, E); T::mat_group_t1(kc, G, madet, E); }
+        else { T::mat_group_t2(kc, G, madet, E); T::mat_group_t3(kc, G, madet, E); }
+    } else {
+        static_assert(LPC == 4, "lanes per cell");
+        switch (part) {
+        case 0: T::mat_group_t0(kc, G, madet, E); break;
+        case 1: T::mat_group_t1(kc, G, madet, E); break;
+        case 2: T::mat_group_t2(kc, G, madet, E); break;
+        default: T::mat_group_t3(kc, G, madet, E); break;
+        }
+    }
+}
+
+// Element tensor entries of this lane's part of a cell, into E.
+template <int D, int K>
+__device__ __forceinline__ void cell_tensor(int part, const CellIn<D> &c, double cstiff, double cmass, double *E)
+{
+    using T = typename TabOf<D, K>::T;
+    constexpr int LPC = MatCfg<D, K>::LPC;
+    if constexpr (MatCfg<D, K>::MT) {
+        double G[Geo<D>::NM], kc[D + 1];
+        const double adet = Geo<D>::metric(c.x, G);
+#pragma unroll
+        for (int m = 0; m <= D; ++m) kc[m] = cstiff * c.k[m];
+        mat_part_t<T, LPC>(part, kc, G, cmass * adet, E);
+    } else {
+        double P[(D + 1) * Geo<D>::NM], madet;
+        tensor_inputs<D>(c, cstiff, cmass, P, &madet);
+        mat_part<T, LPC>(part, P, madet, E);
+    }
+}
+
 // One batch of MAT_BATCH stream indices of a lane.  The lane keeps the
 // running sum of the Mat value it has open in registers (acc, its LDS byte
 // address in cur).  Index i < SCAP opens Mat value i: the open value is
@@ -342,7 +390,7 @@ __device__ __forceinline__ void hold(T &x)
 // loaded into sv ahead of time (every stream has at least one batch), rare
 // longer streams load the rest one batch at a time.  Ends by writing back
 // the value left open.
-template <int SCAP, int ZIDX>
+template <int SCAP, int ZIDX, int NBMAX>
 __device__ __forceinline__ void pull_stream(Batch (&sv)[NBMAX], const Batch *__restrict__ ps, int nb,
                                             double *lds)
 {
@@ -360,12 +408,14 @@ __device__ __forceinline__ void pull_stream(Batch (&sv)[NBMAX], const Batch *__r
 // the chunk's element tensors were computed, so they have long arrived).
 // Done before any younger prefetch is issued, the stream walk then waits for
 // nothing (waits count loads in issue order).
+template <int NBMAX>
 __device__ __forceinline__ void hold_stream(Batch (&sv)[NBMAX])
 {
 #pragma unroll
     for (int i = 0; i < NBMAX; ++i) asm volatile("" : "+v"(sv[i]));
 }
 
+template <int NBMAX>
 __device__ __forceinline__ void load_stream(Batch (&sv)[NBMAX], const Batch *__restrict__ ps, int nb)
 {
 #pragma unroll
@@ -373,11 +423,12 @@ __device__ __forceinline__ void load_stream(Batch (&sv)[NBMAX], const Batch *__r
 }
 
 // Stream of chunk q of a block, for this wave.
+template <int NW>
 __device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, int q, int wave, int lane, int &nb,
                                              const Batch *__restrict__ &ps)
 {
-    const int st = ldc(a.wq + h.w0() + 8 * q + wave);
-    nb = (ldc(a.wq + h.w0() + 8 * q + wave + 1) - st) >> 6;
+    const int st = ldc(a.wq + h.w0() + NW * q + wave);
+    nb = (ldc(a.wq + h.w0() + NW * q + wave + 1) - st) >> 6;
     ps = reinterpret_cast<const Batch *>(a.pstream) + st + lane;
 }
 
@@ -400,13 +451,14 @@ __device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, in
 // register is consumed before a younger load is waited for, so the
 // compiler's waits stay exact and never drain the prefetches.
 template <int D, int K>
-__global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
+__global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, int nblk)
 {
     using T = typename TabOf<D, K>::T;
     using L = MatLds<D, K>;
     constexpr int NE = T::NE, CCH = L::CCH, LPC = MatCfg<D, K>::LPC;
-    constexpr int NP = (D + 1) * Geo<D>::NM;
+    constexpr int MWG = MatCfg<D, K>::WG, NW = MWG / 64;
     constexpr int CO = 4;         // Mat values per lane and round of the write-out
+    static_assert(MWG == 512 || MWG == 1024, "workgroup size");
     static_assert(CCH * LPC <= MWG, "one cell item per lane");
     static_assert(T::NG % LPC == 0, "groups per lane");
     __shared__ double lds[L::TOTAL];
@@ -425,11 +477,11 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
     MatBlk hn = bb + 1 < be ? mat_blk(a, bb + 1) : h;
     int nb = 0;
     const Batch *__restrict__ ps = nullptr;
-    Batch sv[NBMAX];             // first stream batches of the current unit
+    Batch sv[MatCfg<D, K>::NB];  // first stream batches of the current unit
     CellIn<D> cin;               // first-chunk cell data of the current block
     VIds<D> vn;                  // vertex ids of the next block's first-chunk cell
     if (h.nq() > 0) {
-        chunk_stream(a, h, 0, wave, lane, nb, ps);
+        chunk_stream<NW>(a, h, 0, wave, lane, nb, ps);
         load_stream(sv, ps, nb);
     }
     if (has_item && lcc < h.nc()) {
@@ -454,16 +506,12 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
             const bool cx = last ? more && hn.nc() > 0 : true;   // next unit has cells
             int nbx = 0;
             const Batch *__restrict__ psx = ps;
-            if (sx) chunk_stream(a, hx, qx, wave, lane, nbx, psx);
+            if (sx) chunk_stream<NW>(a, hx, qx, wave, lane, nbx, psx);
             // uniform prefetch; lanes past the next chunk's cells load a
             // duplicate of the block's last cell, unused
             const int lcx = qx * CCH + lcc;
             if (cx) vn.load(a.bverts, hx.c0() + (lcx < hx.nc() ? lcx : hx.nc() - 1));
-            if (has_item && q * CCH + lcc < h.nc()) {
-                double P[NP], madet;
-                tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
-                mat_part<T, LPC>(part, P, madet, E);
-            }
+            if (has_item && q * CCH + lcc < h.nc()) cell_tensor<D, K>(part, cin, a.cstiff, a.cmass, E);
             lds_barrier();
             hold_stream(sv);
             if (cx) {
@@ -488,7 +536,7 @@ __global__ __launch_bounds__(MWG) void k_assemble_mat(KArgs a, int nblk)
                 issue_coords<D>(v, a.coords, a.coeff, cin);
             }
             if (hn.nq() > 0) {
-                chunk_stream(a, hn, 0, wave, lane, nb, ps);
+                chunk_stream<NW>(a, hn, 0, wave, lane, nb, ps);
                 load_stream(sv, ps, nb);
             }
         }
@@ -605,7 +653,7 @@ hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
     const int nblk = a.plan->nblk;
     const int grid = std::min(nblk, std::max(a.num_cus, 1));
-    hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(grid), dim3(MWG), 0, s, kargs(a), nblk);
+    hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(grid), dim3(MatCfg<D, K>::WG), 0, s, kargs(a), nblk);
     return hipGetLastError();
 }
 
@@ -617,6 +665,7 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
                               : (degree + 1) * (degree + 2) * (degree + 3) / 6;
     const int lb = lbits_for(nloc);
     out->slot_cap = 0;
+    out->lanes = 0;
     out->ne = nloc * (nloc + 1) / 2;
 #define FEM_LIM(D, K)                                                             \
     if (dim == D && degree == K) {                                                \
@@ -625,6 +674,7 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
             out->slot_cap = MatLds<D, K>::SCAP;                                   \
             out->cell_cap = MatLds<D, K>::CCH * MatCfg<D, K>::MCH;                \
             out->chunk_cells = MatLds<D, K>::CCH;                                 \
+            out->lanes = MatCfg<D, K>::WG;                                        \
         } else {                                                                  \
             out->rows_per_block = VKR * VWG;                                      \
             out->cell_cap = std::min(1 << (16 - lb), VLDS / nloc);                \

@@ -32,7 +32,8 @@ struct fem_ctx {
 //    ascending cell id, the same order in every block, so the sums are
 //    reproducible and an assembled symmetric form is bitwise symmetric.
 //    The stream of (chunk q, wave w) of a block starts at batch index
-//    wq[blk_w[b] + 8q + w] and ends where the next one starts; inside it,
+//    wq[blk_w[b] + W q + w] (W waves per workgroup) and ends where the next
+//    one starts; inside it,
 //    batch i of lane l is the batch at start + 64 i + l (femk::MAT_BATCH
 //    indices, two per 32-bit word, the first in the low half).
 struct fem_plan {
@@ -154,6 +155,7 @@ struct Limits {
     int cell_cap;           // distinct cells per block
     int chunk_cells;        // Mat: cells whose element tensors share LDS at once (one chunk)
     int ne;                 // doubles per packed element tensor (Mat only)
+    int lanes;              // Mat: lanes of the workgroup (the streams are dealt to them)
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
 

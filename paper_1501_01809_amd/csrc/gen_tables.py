@@ -17,6 +17,12 @@ to l_m (chain rule: grad phi = sum_m d_m phi grad l_m).  All integrals are
 exact rationals (int_ref l^a = a!/(|a|+d)!), rounded once to double and
 printed as hexadecimal literals; zero terms are dropped at generation time.
 
+Each element tensor is emitted twice: from P (mat_group*, act) and from
+kc[k] = cstiff kappa_k and the metric G[mn] = |det J| grad l_m . grad l_n
+with the terms of an entry grouped by metric pair (mat_group_t*, act_t),
+A_ij = sum_mn G[mn] (sum_k W[k][mn][i][j] kc[k]) + madet Mref_ij, which keeps
+d+1 + NM values live instead of (d+1) x NM.
+
 Local node order: vertices; edges (a<b lexicographic), the two P3 edge nodes
 ordered from a; P3 tetrahedron faces (a<b<c lexicographic) or the P3
 triangle's interior node.
@@ -255,6 +261,30 @@ def emit(d, k, G):
                 out.append("      " + l)
             out.append(f"      E[{upper_index(i, j, n)}] = e;")
             out.append("    }")
+        out.append("  }")
+    # the same entry groups from kc[k] = cstiff kappa_k and the metric G[mn]
+    # (terms grouped by metric pair: d+1 + NM values live instead of P)
+    nv_ = d + 1
+    for g, grp in enumerate(groups):
+        out.append(f"  // entries of group {g} from kc and the metric, written to E[NE]")
+        out.append(f"  __device__ __forceinline__ static void mat_group_t{g}(const double* __restrict__ kc, const double* __restrict__ G, double madet, double* __restrict__ E) {{")
+        for (i, j) in grp:
+            byt = {}
+            for (kk, t, w) in stiff[(i, j)]:
+                byt.setdefault(t, {})[kk] = w
+            expr = None
+            mw = mass[(i, j)]
+            if mw != 0:
+                expr = f"{hexlit(mw)} * madet"
+            for t in sorted(byt):
+                dot = None
+                for kk in range(nv_):
+                    w = byt[t].get(kk, Fraction(0))
+                    if w == 0:
+                        continue
+                    dot = f"{hexlit(w)} * kc[{kk}]" if dot is None else f"__builtin_fma({hexlit(w)}, kc[{kk}], {dot})"
+                expr = f"G[{t}] * ({dot})" if expr is None else f"__builtin_fma(G[{t}], ({dot}), {expr})"
+            out.append(f"    E[{upper_index(i, j, n)}] = {expr if expr else '0.0'};")
         out.append("  }")
     out.append("  // upper triangle, row-major (i<=j), Eu[NE]")
     out.append("  __device__ __forceinline__ static void mat_upper(const double* __restrict__ P, double madet, double* __restrict__ Eu) {")
