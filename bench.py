@@ -502,7 +502,7 @@ def main():
                          "HBM byte counters of a profiler, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        sys.exit("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        sys.exit("bench.py runs on exactly one GPU: the library has no multi-GPU path "
                  "(one GPU's share of the mesh is the measured unit).")
 
     import torch
