@@ -371,9 +371,9 @@ fem_status fem_par_loop_assemble_facets(fem_ctx *ctx, const fem_plan *plan, cons
  * Firedrake example assembles A with a DirichletBC and applies it to b).  For
  * every row r with mask[r] != 0: row r and column r of A become zero except
  * A[r][r] = diag, and b[r] = diag g[r].  Every other row i first lifts the
- * boundary values, b[i] -= A[i][r] g[r] for its boundary columns r (column
- * order), so that the modified system keeps the solution and stays
- * symmetric.  mask: uint8 [nrows] device; values: the Mat's values in sp's
+ * boundary values, b[i] -= sum of A[i][r] g[r] over its boundary columns r
+ * (summed in a fixed order: bitwise reproducible), so that the modified
+ * system keeps the solution and stays symmetric.  mask: uint8 [nrows] device; values: the Mat's values in sp's
  * order; b and g: float64 [nrows] device, g NULL for homogeneous conditions,
  * b NULL to modify A only (then g must be NULL).  Square Mats only.
  * Asynchronous; allocates nothing.
