@@ -129,11 +129,19 @@ template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH =
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4, WG = 1024, NB = 4; static constexpr bool MT = false; };
 template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 
-// Dat and action kernels: workgroups of VWG lanes, KR rows per lane; the
+// Dat and action kernels: workgroups of WG lanes, KR rows per lane; the
 // per-cell local vectors of the whole block live in LDS (VLDS doubles, two
 // workgroups per CU).
 constexpr int VWG = 512;
 constexpr int VKR = 2;
+constexpr int VROWS = VKR * VWG;   // rows of a Dat plan block
+// The source vector's kernel needs few registers: it runs VROWS lanes of one
+// row each (twice the waves per CU: P2 tetrahedra 85 -> 68 us), except on P3
+// tetrahedra, whose 78 VGPRs would then leave room for one workgroup per CU;
+// the action keeps VWG lanes of VKR rows.
+template <int D, int K, bool ACTION> struct VecWG {
+    static constexpr int WG = ACTION || (D == 3 && K == 3) ? VWG : VROWS, KR = VROWS / WG;
+};
 constexpr int VLDS = LDS_DOUBLES / 2;
 constexpr int VPRE = 8;     // entries of a row fetched per batch
 // Action: METRIC evaluates y_K = A_K x_K from the cstiff-scaled nodal kappa
@@ -565,8 +573,9 @@ __global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, in
 // ---------------------------------------------------------------- Dat / action
 
 template <int D, int K, bool ACTION>
-__global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
+__global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArgs a)
 {
+    constexpr int WG = VecWG<D, K, ACTION>::WG, KR = VecWG<D, K, ACTION>::KR;
     using T = typename TabOf<D, K>::T;
     constexpr int NL = T::NLOC, LB = lbits_for(NL);
     constexpr int NP = (D + 1) * Geo<D>::NM;
@@ -587,7 +596,7 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
         }
     };
     if (PRE && tid < nc) fetch(tid);
-    for (int cs = 0; cs < nc; cs += VWG) {
+    for (int cs = 0; cs < nc; cs += WG) {
         if (cs + tid < nc) {
             if (!PRE) fetch(cs + tid);
             double loc[NL];
@@ -611,16 +620,16 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
 #pragma unroll
             for (int j = 0; j < NL; ++j) vk[(cs + tid) * NL + j] = loc[j];
         }
-        if (PRE && cs + VWG + tid < nc) fetch(cs + VWG + tid);
+        if (PRE && cs + WG + tid < nc) fetch(cs + WG + tid);
     }
     // the rows' first entries are fetched only now, so that they hold no
     // registers while the cells are evaluated
-    int cur[VKR], end[VKR];
-    uint32_t pe[VKR][VPRE];
-    double acc[VKR];
+    int cur[KR], end[KR];
+    uint32_t pe[KR][VPRE];
+    double acc[KR];
 #pragma unroll
-    for (int k = 0; k < VKR; ++k) {
-        const int r = r0 + tid + VWG * k;
+    for (int k = 0; k < KR; ++k) {
+        const int r = r0 + tid + WG * k;
         cur[k] = r < r1 ? a.inc_ptr[r] : 0;
         end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
         acc[k] = 0.0;
@@ -630,7 +639,7 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
     lds_barrier();
     // every row sums its cells' local values in ascending cell order
 #pragma unroll
-    for (int k = 0; k < VKR; ++k) {
+    for (int k = 0; k < KR; ++k) {
         while (cur[k] < end[k]) {
 #pragma unroll
             for (int m = 0; m < VPRE; ++m)
@@ -642,8 +651,8 @@ __global__ __launch_bounds__(VWG) void k_assemble_vec(KArgs a)
         }
     }
 #pragma unroll
-    for (int k = 0; k < VKR; ++k) {
-        const int r = r0 + tid + VWG * k;
+    for (int k = 0; k < KR; ++k) {
+        const int r = r0 + tid + WG * k;
         if (r < r1) a.out[r] = a.inc ? a.out[r] + acc[k] : acc[k];
     }
 }
@@ -676,7 +685,7 @@ bool limits(int dim, int degree, bool is_mat, Limits *out)
             out->chunk_cells = MatLds<D, K>::CCH;                                 \
             out->lanes = MatCfg<D, K>::WG;                                        \
         } else {                                                                  \
-            out->rows_per_block = VKR * VWG;                                      \
+            out->rows_per_block = VROWS;                                          \
             out->cell_cap = std::min(1 << (16 - lb), VLDS / nloc);                \
         }                                                                         \
         return true;                                                              \
@@ -701,13 +710,13 @@ namespace {
 template <int D, int K>
 hipError_t vec_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_assemble_vec<D, K, false>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
+    hipLaunchKernelGGL((k_assemble_vec<D, K, false>), dim3(a.plan->nblk), dim3(VecWG<D, K, false>::WG), 0, s, kargs(a));
     return hipGetLastError();
 }
 template <int D, int K>
 hipError_t action_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_assemble_vec<D, K, true>), dim3(a.plan->nblk), dim3(VWG), 0, s, kargs(a));
+    hipLaunchKernelGGL((k_assemble_vec<D, K, true>), dim3(a.plan->nblk), dim3(VecWG<D, K, true>::WG), 0, s, kargs(a));
     return hipGetLastError();
 }
 }  // namespace
