@@ -116,12 +116,17 @@ typedef enum fem_kind {
 typedef struct fem_set { int64_t size; } fem_set;
 
 /* A Map from->to of constant arity: values[e*arity + l] in [0, to->size),
- * int32, row-major [from->size][arity], device memory ("Maps"). */
+ * int32, row-major [from->size][arity], device memory ("Maps").  version:
+ * the caller's count of changes to the contents of values.  A plan records
+ * the array and the version of every Map it was built from; a call with the
+ * same array at another version (contents rewritten in place) is refused
+ * with FEM_E_ARG, so that a stale plan is never applied. */
 typedef struct fem_map {
     const fem_set *from;
     const fem_set *to;
     int32_t arity;
     const int32_t *values;
+    uint64_t version;
 } fem_map;
 
 /* A Dat: set->size * dim float64 values, node-major [size][dim], device
@@ -155,13 +160,21 @@ typedef struct fem_global {
 
 /* The local kernel: form kind, cell shape, Lagrange degree of the test and
  * trial space (1..3), value dimension of that space (1; 3 for
- * FEM_ELASTICITY), contraction precision. */
+ * FEM_ELASTICITY), contraction precision, quadrature degree.
+ * qdegree: 0 (or any degree at least the integrand's) selects exact
+ * integration, which is what every kernel does: each integrand is a
+ * polynomial (degree 2k of P_k test and trial functions with a P1
+ * coefficient, k+1 for the source, 4 for the P1 residual, 3 for elasticity)
+ * integrated by exact reference tensors rounded once, so any exact rule gives
+ * the same values up to rounding.  A positive qdegree below the integrand's
+ * degree (an under-integrated form) is FEM_E_UNSUPPORTED. */
 typedef struct fem_form {
     fem_kind kind;
     fem_cell cell;
     int32_t degree;
     int32_t dim;
     fem_prec prec;
+    int32_t qdegree;
 } fem_form;
 
 /* par_loop data arguments other than the output: the iteration Set (cells),
@@ -197,6 +210,22 @@ typedef struct fem_plan fem_plan;
 fem_status fem_ctx_create(int device, void *hip_stream, fem_ctx **ctx);
 void fem_ctx_destroy(fem_ctx *ctx);
 fem_status fem_ctx_set_stream(fem_ctx *ctx, void *hip_stream);
+/* Device memory of the context from the caller's allocator (for instance
+ * torch's caching allocator): alloc(bytes, user) returns device memory on the
+ * context's device, usable on the context's stream, or NULL (the call then
+ * fails with FEM_E_NOMEM); release(ptr, user) gives it back.  Plans created
+ * afterwards take their arrays from it and release them in fem_plan_destroy
+ * (the allocator must outlive them); temporaries of the setup calls
+ * (fem_build_sparsity without a work buffer, fem_plan_create,
+ * fem_renumber, fem_facet_plan_create) are allocated and released inside
+ * the call: a release may come before work queued on the context stream has
+ * run, so the allocator must order reuse on that stream (torch's caching
+ * allocator does, for memory allocated on it).  alloc == NULL and
+ * release == NULL restore the HIP runtime (hipMalloc for plans, stream-
+ * ordered hipMallocAsync for temporaries).  FEM_E_ARG if exactly one of the
+ * two is NULL. */
+fem_status fem_ctx_set_allocator(fem_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                                 void (*release)(void *ptr, void *user), void *user);
 /* Text of the last failure on this context ("" if none); owned by ctx. */
 const char *fem_last_error(const fem_ctx *ctx);
 /* Synchronise the context stream; FEM_E_DEVICE on a pending device error. */
@@ -213,11 +242,21 @@ fem_status fem_sync(fem_ctx *ctx);
  *   2. sp->col_idx != NULL (nnz entries, caller-allocated), row_ptr from the
  *      first call: fills the columns.  Does not synchronise.
  * FEM_E_RANGE if a Map entry is out of range, FEM_E_OVERFLOW if nnz or the
- * incidence count does not fit the library's int32 column/entry indices.
- * Temporary device memory is allocated and freed inside the call.
+ * incidence count does not fit the library's int32 column/entry indices,
+ * FEM_E_UNSUPPORTED if the cells around one row reach more than 2048
+ * candidate columns (counted with repetition; about 100 cells around a vertex
+ * at P3).
+ * Scratch device memory: work_bytes == NULL: the call takes it from the
+ * context's allocator and gives it back before returning.  work_bytes !=
+ * NULL and work == NULL: a query; *work_bytes receives the bytes the call
+ * needs for these Maps (the same for both passes) and nothing else is done.
+ * work != NULL: the caller's buffer of *work_bytes bytes (at least the
+ * queried size, else FEM_E_ARG, 256-byte aligned), used as scratch; the call
+ * then allocates nothing.  The buffer is in use until the queued work has
+ * run.
  */
 fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap,
-                              fem_sparsity *sp);
+                              fem_sparsity *sp, void *work, size_t *work_bytes);
 
 /*
  * Sparsity of a vector-valued space from the node sparsity: every node entry

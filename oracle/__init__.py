@@ -57,13 +57,13 @@ def lib():
         L.oracle_element_matrix.argtypes = [I, I, P, P, D, D, P, P]; L.oracle_element_matrix.restype = I
         L.oracle_element_vector.argtypes = [I, I, P, P, P, P]; L.oracle_element_vector.restype = I
         L.oracle_sparsity.argtypes = [L64, I, P, I, P, L64, L64, P, P]; L.oracle_sparsity.restype = L64
-        L.oracle_assemble_mat.argtypes = [I, I, L64, P, P, P, P, D, D, P, P, L64, P, P]
+        L.oracle_assemble_mat.argtypes = [I, I, L64, P, P, P, P, D, D, P, P, L64, P, P, P]
         L.oracle_assemble_mat.restype = I
         L.oracle_assemble_vec.argtypes = [I, I, L64, P, P, P, P, L64, P, P]
         L.oracle_assemble_vec.restype = I
         L.oracle_apply_action.argtypes = [I, I, L64, P, P, P, P, D, D, P, L64, P, P]
         L.oracle_apply_action.restype = I
-        L.oracle_mat_rows.argtypes = [I, I, L64, P, P, P, P, D, D, L64, L64, P, L64, P, P, P, P]
+        L.oracle_mat_rows.argtypes = [I, I, L64, P, P, P, P, D, D, L64, L64, P, L64, P, P, P, P, P]
         L.oracle_mat_rows.restype = L64
         L.oracle_vec_rows.argtypes = [I, I, I, L64, P, P, P, P, D, D, P, L64, L64, P, P, P]
         L.oracle_vec_rows.restype = I
@@ -166,17 +166,25 @@ def sparsity(rmap, nrows, cmap=None, ncols=None):
 
 
 def assemble_mat(dim, degree, cell_vertex, coords, cell_node, kappa, row_ptr, col_idx,
-                 form="helmholtz"):
+                 form="helmholtz", contrib_scale=False):
+    """Assembled CSR values and the term-level rounding scale of each entry
+    (sum over cells and quadrature points of |weight * integrand term|); with
+    contrib_scale also the contribution-level scale (sum over cells of
+    |element entry|), which is never larger."""
     cs, cm = FORMS[form]
     cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
     k = _c(kappa, np.float64); rp = _c(row_ptr, np.int64); ci = _c(col_idx, np.int32)
     nrows = rp.size - 1
     vals = np.zeros(max(int(rp[-1]), 1)); absv = np.zeros_like(vals)
+    cabs = np.zeros_like(vals) if contrib_scale else None
     rc = lib().oracle_assemble_mat(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k),
-                                   cs, cm, _p(rp), _p(ci), nrows, _p(vals), _p(absv))
+                                   cs, cm, _p(rp), _p(ci), nrows, _p(vals), _p(absv),
+                                   _p(cabs) if contrib_scale else None)
     if rc:
         raise RuntimeError(f"oracle assemble_mat failed ({rc})")
     nnz = int(rp[-1])
+    if contrib_scale:
+        return vals[:nnz], absv[:nnz], cabs[:nnz]
     return vals[:nnz], absv[:nnz]
 
 
@@ -205,21 +213,28 @@ def apply_action(dim, degree, cell_vertex, coords, cell_node, kappa, x, nrows,
 
 
 def mat_rows(dim, degree, cell_vertex, coords, cell_node, kappa, nrows, rows,
-             form="helmholtz"):
-    """Assembled rows ``rows`` (distinct): list of (cols, vals, abs) per row."""
+             form="helmholtz", contrib_scale=False):
+    """Assembled rows ``rows`` (distinct): list of (cols, vals, abs) per row,
+    abs the term-level scale; with contrib_scale (cols, vals, abs, cabs), cabs
+    the contribution-level scale (sum over cells of |element entry|)."""
     cs, cm = FORMS[form]
     cv = _c(cell_vertex, np.int32); X = _c(coords, np.float64); cn = _c(cell_node, np.int32)
     k = _c(kappa, np.float64); rows = _c(rows, np.int64)
     cap = rows.size * 1024
     ptr = np.zeros(rows.size + 1, dtype=np.int64)
     cols = np.zeros(cap, dtype=np.int32); vals = np.zeros(cap); absv = np.zeros(cap)
+    cabs = np.zeros(cap)
     tot = lib().oracle_mat_rows(dim, degree, cv.shape[0], _p(cv), _p(X), _p(cn), _p(k), cs, cm,
                                 nrows, rows.size, _p(rows), cap, _p(ptr), _p(cols), _p(vals),
-                                _p(absv))
+                                _p(absv), _p(cabs))
     if tot < 0:
         raise RuntimeError(f"oracle mat_rows failed ({tot})")
-    return [(cols[ptr[s]:ptr[s + 1]].copy(), vals[ptr[s]:ptr[s + 1]].copy(),
-             absv[ptr[s]:ptr[s + 1]].copy()) for s in range(rows.size)]
+    out = []
+    for s in range(rows.size):
+        sl = slice(ptr[s], ptr[s + 1])
+        t = (cols[sl].copy(), vals[sl].copy(), absv[sl].copy())
+        out.append(t + (cabs[sl].copy(),) if contrib_scale else t)
+    return out
 
 
 def vec_rows(dim, degree, cell_vertex, coords, cell_node, f, nrows, rows):

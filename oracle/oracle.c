@@ -484,13 +484,15 @@ static int64_t find_col(const int64_t *row_ptr, const int32_t *col_idx, int64_t 
 int oracle_assemble_mat(int dim, int degree, int64_t ncells, const int32_t *cell_vertex,
                         const double *coords, const int32_t *cell_node, const double *kappa,
                         double cstiff, double cmass, const int64_t *row_ptr,
-                        const int32_t *col_idx, int64_t nrows, double *values, double *absval)
+                        const int32_t *col_idx, int64_t nrows, double *values, double *absval,
+                        double *cabsval)
 {
     const int n = oracle_nloc(dim, degree);
     if (n < 0) return -1;
     int64_t nnz = row_ptr[nrows];
     memset(values, 0, sizeof(double) * (size_t)nnz);
     if (absval) memset(absval, 0, sizeof(double) * (size_t)nnz);
+    if (cabsval) memset(cabsval, 0, sizeof(double) * (size_t)nnz);
     double xv[12], kv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC];
     for (int64_t c = 0; c < ncells; ++c) {
         gather_cell(dim, c, cell_vertex, coords, kappa, xv, kv);
@@ -502,6 +504,8 @@ int oracle_assemble_mat(int dim, int degree, int64_t ncells, const int32_t *cell
                 if (k < 0) return -3;
                 values[k] += A[i * n + j];
                 if (absval) absval[k] += Aa[i * n + j];
+                /* contribution-level scale: sum over cells of |element entry| */
+                if (cabsval) cabsval[k] += fabs(A[i * n + j]);
             }
         }
     }
@@ -574,7 +578,7 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
                         const double *coords, const int32_t *cell_node, const double *kappa,
                         double cstiff, double cmass, int64_t nrows, int64_t nsel,
                         const int64_t *rows, int64_t cap, int64_t *out_ptr,
-                        int32_t *out_cols, double *out_vals, double *out_abs)
+                        int32_t *out_cols, double *out_vals, double *out_abs, double *out_cabs)
 {
     const int n = oracle_nloc(dim, degree);
     if (n < 0) return -1;
@@ -583,8 +587,12 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
     int32_t *cols = malloc(sizeof(int32_t) * (size_t)(nsel * per));
     double *vals = calloc((size_t)(nsel * per), sizeof(double));
     double *abss = calloc((size_t)(nsel * per), sizeof(double));
+    double *cabs = calloc((size_t)(nsel * per), sizeof(double));
     int64_t *cnt = calloc((size_t)nsel, sizeof(int64_t));
-    if (!slot || !cols || !vals || !abss || !cnt) { free(slot); free(cols); free(vals); free(abss); free(cnt); return -1; }
+    if (!slot || !cols || !vals || !abss || !cabs || !cnt) {
+        free(slot); free(cols); free(vals); free(abss); free(cabs); free(cnt);
+        return -1;
+    }
     for (int64_t r = 0; r < nrows; ++r) slot[r] = -1;
     for (int64_t s = 0; s < nsel; ++s) slot[rows[s]] = s;
     double xv[12], kv[4], A[MAXLOC * MAXLOC], Aa[MAXLOC * MAXLOC];
@@ -608,6 +616,7 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
                 }
                 vals[s * per + k] += A[i * n + j];
                 abss[s * per + k] += Aa[i * n + j];
+                cabs[s * per + k] += fabs(A[i * n + j]);
             }
         }
     }
@@ -615,23 +624,27 @@ int64_t oracle_mat_rows(int dim, int degree, int64_t ncells, const int32_t *cell
     if (rc == 0) {
         out_ptr[0] = 0;
         for (int64_t s = 0; s < nsel; ++s) {
-            /* insertion sort of this row's (col, val, abs) triples by col */
-            int32_t *cc = cols + s * per; double *vv = vals + s * per, *aa = abss + s * per;
+            /* insertion sort of this row's (col, val, abs, cabs) tuples by col */
+            int32_t *cc = cols + s * per;
+            double *vv = vals + s * per, *aa = abss + s * per, *ca = cabs + s * per;
             for (int64_t a = 1; a < cnt[s]; ++a) {
-                int32_t kc = cc[a]; double kv2 = vv[a], ka = aa[a];
+                int32_t kc = cc[a]; double kv2 = vv[a], ka = aa[a], kca = ca[a];
                 int64_t b = a - 1;
-                while (b >= 0 && cc[b] > kc) { cc[b + 1] = cc[b]; vv[b + 1] = vv[b]; aa[b + 1] = aa[b]; --b; }
-                cc[b + 1] = kc; vv[b + 1] = kv2; aa[b + 1] = ka;
+                while (b >= 0 && cc[b] > kc) {
+                    cc[b + 1] = cc[b]; vv[b + 1] = vv[b]; aa[b + 1] = aa[b]; ca[b + 1] = ca[b]; --b;
+                }
+                cc[b + 1] = kc; vv[b + 1] = kv2; aa[b + 1] = ka; ca[b + 1] = kca;
             }
             if (total + cnt[s] > cap) { rc = -5; break; }
             memcpy(out_cols + total, cc, sizeof(int32_t) * (size_t)cnt[s]);
             memcpy(out_vals + total, vv, sizeof(double) * (size_t)cnt[s]);
             memcpy(out_abs + total, aa, sizeof(double) * (size_t)cnt[s]);
+            if (out_cabs) memcpy(out_cabs + total, ca, sizeof(double) * (size_t)cnt[s]);
             total += cnt[s];
             out_ptr[s + 1] = total;
         }
     }
-    free(slot); free(cols); free(vals); free(abss); free(cnt);
+    free(slot); free(cols); free(vals); free(abss); free(cabs); free(cnt);
     return rc ? rc : total;
 }
 

@@ -56,19 +56,41 @@ bool dat_ok(const fem_dat *d, const fem_set *set, int dim)
     return d && d->set && d->dim == dim && d->set->size == set->size && (d->data || set->size == 0);
 }
 
-// Device buffer freed at scope exit (setup paths only).
+// Temporary device buffer of a setup call, from the context's allocator,
+// released at scope exit (stream-ordered on the context stream).
 struct DevBuf {
     void *p = nullptr;
-    hipStream_t s = nullptr;
-    explicit DevBuf(hipStream_t st) : s(st) {}
-    hipError_t alloc(size_t bytes) { return hipMallocAsync(&p, bytes ? bytes : 8, s); }
-    ~DevBuf() { if (p) (void)hipFreeAsync(p, s); }
+    const fem_ctx *ctx;
+    explicit DevBuf(const fem_ctx *c) : ctx(c) {}
+    hipError_t alloc(size_t bytes) { return femk::mem_alloc(ctx->mem, ctx->stream, true, bytes ? bytes : 8, &p); }
+    ~DevBuf() { if (p) femk::mem_free(ctx->mem, ctx->stream, true, p); }
     template <typename T> T *as() const { return (T *)p; }
+};
+
+// Carves a caller's scratch buffer into 256-byte aligned pieces (or sizes it
+// when base is NULL).
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    template <typename T> T *take(int64_t n)
+    {
+        T *q = base ? (T *)(base + off) : nullptr;
+        off += ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) / 256 * 256;
+        return q;
+    }
 };
 
 fem_status check_form(fem_ctx *ctx, const fem_form *f)
 {
     if (!f) return fail(ctx, FEM_E_ARG, "form is NULL");
+    // exact integration: the integrand's polynomial degree (P1 coefficients)
+    const int qexact = f->kind == FEM_ELASTICITY ? 3 : f->kind == FEM_NL_RESIDUAL ? 4
+                       : f->kind == FEM_SOURCE ? f->degree + 1 : 2 * f->degree;
+    if (f->qdegree < 0 || (f->qdegree > 0 && f->qdegree < qexact))
+        return fail(ctx, FEM_E_UNSUPPORTED,
+                    "quadrature degree %d: the kernels integrate exactly (degree %d for this form); "
+                    "an under-integrated rule is not provided", f->qdegree, qexact);
     if (f->kind == FEM_ELASTICITY) {
         if (f->prec < FEM_FP64 || f->prec > FEM_FP16)
             return fail(ctx, FEM_E_UNSUPPORTED, "precision %d not supported", (int)f->prec);
@@ -129,7 +151,7 @@ void form_coeffs(fem_kind k, double *cstiff, double *cmass)
 fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *name)
 {
     int hflag = 0;
-    HIPC(hipMemsetAsync(dflag, 0, sizeof(int), ctx->stream), "memset");
+    HIPC(femk::fill_i32(dflag, 1, 0, ctx->stream), "clear flag");
     HIPC(femk::check_range(m->values, m->from->size * (int64_t)m->arity, m->to->size, dflag, ctx->stream),
          "range check");
     HIPC(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "copy");
@@ -145,14 +167,14 @@ void free_plan_arrays(fem_plan *p)
                     p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work, p->red_partial,
                     p->f_ptr, p->f_ent, p->f_work};
     for (void *q : arrs)
-        if (q) (void)hipFree(q);
+        if (q) femk::mem_free(p->mem, nullptr, false, q);
 }
 
 template <typename T>
-hipError_t upload(T **dst, const std::vector<T> &src, size_t *bytes, hipStream_t s)
+hipError_t upload(const fem_mem &m, T **dst, const std::vector<T> &src, size_t *bytes, hipStream_t s)
 {
     size_t n = src.size() * sizeof(T);
-    hipError_t e = hipMalloc((void **)dst, n ? n : 8);
+    hipError_t e = femk::mem_alloc(m, s, false, n ? n : 8, (void **)dst);
     if (e != hipSuccess) return e;
     *bytes += n;
     if (n) e = hipMemcpyAsync(*dst, src.data(), n, hipMemcpyHostToDevice, s);
@@ -246,6 +268,28 @@ void sfc_order(const std::vector<double> &pos, int dim, int64_t n, int32_t *perm
 
 }  // namespace
 
+namespace femk {
+
+hipError_t mem_alloc(const fem_mem &m, hipStream_t s, bool temp, size_t bytes, void **p)
+{
+    *p = nullptr;
+    if (m.alloc) {
+        *p = m.alloc(bytes, m.user);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return temp ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+}
+
+void mem_free(const fem_mem &m, hipStream_t s, bool temp, void *p)
+{
+    if (!p) return;
+    if (m.release) m.release(p, m.user);
+    else if (temp) (void)hipFreeAsync(p, s);
+    else (void)hipFree(p);
+}
+
+}  // namespace femk
+
 extern "C" {
 
 fem_status fem_ctx_create(int device, void *hip_stream, fem_ctx **out)
@@ -275,6 +319,17 @@ fem_status fem_ctx_set_stream(fem_ctx *ctx, void *hip_stream)
     return FEM_OK;
 }
 
+fem_status fem_ctx_set_allocator(fem_ctx *ctx, void *(*alloc)(size_t, void *), void (*release)(void *, void *),
+                                 void *user)
+{
+    if (!ctx) return FEM_E_ARG;
+    if (!alloc != !release) return fail(ctx, FEM_E_ARG, "set_allocator: give both alloc and release, or neither");
+    ctx->mem.alloc = alloc;
+    ctx->mem.release = release;
+    ctx->mem.user = alloc ? user : nullptr;
+    return FEM_OK;
+}
+
 const char *fem_last_error(const fem_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
 fem_status fem_sync(fem_ctx *ctx)
@@ -287,42 +342,54 @@ fem_status fem_sync(fem_ctx *ctx)
     return FEM_OK;
 }
 
-fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, fem_sparsity *sp)
+namespace {
+
+// Scratch of the sparsity build, carved from one buffer: the range/overflow
+// flag, the row incidence (ptr, ent), the per-row counts and the scan's tile
+// sums.
+struct SparsityScratch {
+    int *flag;
+    int64_t *ptr, *scan;
+    int32_t *ent, *tmp;
+    size_t bytes;
+    SparsityScratch(void *base, int64_t ncells, int arity, int64_t nrows)
+    {
+        Carve c(base);
+        flag = c.take<int>(64);
+        ptr = c.take<int64_t>(nrows + 1);
+        scan = c.take<int64_t>(femk::scan_scratch(nrows));
+        ent = c.take<int32_t>(ncells * arity);
+        tmp = c.take<int32_t>(nrows + 1);
+        bytes = c.off;
+    }
+};
+
+// The two passes of fem_build_sparsity on scratch w (arguments checked).
+fem_status sparsity_passes(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, fem_sparsity *sp,
+                           const SparsityScratch &w)
 {
-    if (!ctx) return FEM_E_ARG;
-    if (!map_ok(rmap) || !map_ok(cmap) || !sp || !sp->row_ptr)
-        return fail(ctx, FEM_E_ARG, "build_sparsity: malformed Map or NULL row_ptr");
-    if (rmap->from->size != cmap->from->size)
-        return fail(ctx, FEM_E_ARG, "build_sparsity: row and column Maps start from different Sets");
     const int64_t ncells = rmap->from->size, nrows = rmap->to->size, ncols = cmap->to->size;
-    if (ncells * (int64_t)rmap->arity > INT32_MAX || ncells * (int64_t)cmap->arity > INT32_MAX ||
-        nrows > INT32_MAX || ncols > INT32_MAX)
-        return fail(ctx, FEM_E_OVERFLOW, "build_sparsity: more than 2^31-1 entries");
     hipStream_t s = ctx->stream;
     const bool counting = sp->col_idx == nullptr;
-    DevBuf flag(s), ptr(s), ent(s), tmp(s);
-    HIPC(flag.alloc(sizeof(int)), "alloc");
     if (counting) {
-        fem_status st = range_check(ctx, rmap, flag.as<int>(), "row Map");
+        fem_status st = range_check(ctx, rmap, w.flag, "row Map");
         if (st != FEM_OK) return st;
-        st = range_check(ctx, cmap, flag.as<int>(), "column Map");
+        st = range_check(ctx, cmap, w.flag, "column Map");
         if (st != FEM_OK) return st;
+    } else if (sp->nrows != nrows || sp->ncols != ncols) {
+        return fail(ctx, FEM_E_ARG, "build_sparsity: sparsity was counted for other Maps");
     }
-    HIPC(ptr.alloc(sizeof(int64_t) * (nrows + 1)), "alloc");
-    HIPC(ent.alloc(sizeof(int32_t) * (ncells * rmap->arity)), "alloc");
-    HIPC(tmp.alloc(sizeof(int32_t) * (nrows + 1)), "alloc");
-    HIPC(femk::build_incidence(rmap->values, ncells, rmap->arity, nrows, ptr.as<int64_t>(),
-                               ent.as<int32_t>(), tmp.as<int32_t>(), s),
+    HIPC(femk::build_incidence(rmap->values, ncells, rmap->arity, nrows, w.ptr, w.ent, w.tmp, w.scan, s),
          "incidence");
-    HIPC(hipMemsetAsync(flag.p, 0, sizeof(int), s), "memset");
+    HIPC(femk::fill_i32(w.flag, 1, 0, s), "clear flag");
     if (counting) {
-        HIPC(femk::row_columns(ptr.as<int64_t>(), ent.as<int32_t>(), rmap->arity, cmap->values,
-                               cmap->arity, nrows, tmp.as<int32_t>(), nullptr, nullptr, flag.as<int>(), s),
+        HIPC(femk::row_columns(w.ptr, w.ent, rmap->arity, cmap->values, cmap->arity, nrows, w.tmp, nullptr,
+                               nullptr, w.flag, s),
              "row columns");
-        HIPC(femk::exclusive_scan(tmp.as<int32_t>(), sp->row_ptr, nrows, s), "scan");
+        HIPC(femk::exclusive_scan(w.tmp, sp->row_ptr, nrows, w.scan, s), "scan");
         int hflag = 0;
         int64_t nnz = 0;
-        HIPC(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+        HIPC(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
         HIPC(hipMemcpyAsync(&nnz, sp->row_ptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
         HIPC(hipStreamSynchronize(s), "sync");
         if (hflag)
@@ -331,13 +398,50 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
         sp->ncols = ncols;
         sp->nnz = nnz;
     } else {
-        if (sp->nrows != nrows || sp->ncols != ncols)
-            return fail(ctx, FEM_E_ARG, "build_sparsity: sparsity was counted for other Maps");
-        HIPC(femk::row_columns(ptr.as<int64_t>(), ent.as<int32_t>(), rmap->arity, cmap->values,
-                               cmap->arity, nrows, nullptr, sp->row_ptr, sp->col_idx, flag.as<int>(), s),
+        HIPC(femk::row_columns(w.ptr, w.ent, rmap->arity, cmap->values, cmap->arity, nrows, nullptr, sp->row_ptr,
+                               sp->col_idx, w.flag, s),
              "row columns");
     }
     return FEM_OK;
+}
+
+fem_status check_sparsity_args(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, const fem_sparsity *sp)
+{
+    if (!map_ok(rmap) || !map_ok(cmap) || !sp || !sp->row_ptr)
+        return fail(ctx, FEM_E_ARG, "build_sparsity: malformed Map or NULL row_ptr");
+    if (rmap->from->size != cmap->from->size)
+        return fail(ctx, FEM_E_ARG, "build_sparsity: row and column Maps start from different Sets");
+    const int64_t ncells = rmap->from->size, nrows = rmap->to->size, ncols = cmap->to->size;
+    if (ncells * (int64_t)rmap->arity > INT32_MAX || ncells * (int64_t)cmap->arity > INT32_MAX ||
+        nrows > INT32_MAX || ncols > INT32_MAX)
+        return fail(ctx, FEM_E_OVERFLOW, "build_sparsity: more than 2^31-1 entries");
+    return FEM_OK;
+}
+
+}  // namespace
+
+fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, fem_sparsity *sp,
+                              void *work, size_t *work_bytes)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_sparsity_args(ctx, rmap, cmap, sp);
+    if (st != FEM_OK) return st;
+    const int64_t ncells = rmap->from->size, nrows = rmap->to->size;
+    const size_t need = SparsityScratch(nullptr, ncells, rmap->arity, nrows).bytes;
+    if (work_bytes && !work) {
+        *work_bytes = need;
+        return FEM_OK;
+    }
+    if (work) {
+        if (!work_bytes || *work_bytes < need)
+            return fail(ctx, FEM_E_ARG, "build_sparsity: work buffer of %zu bytes, %zu needed",
+                        work_bytes ? *work_bytes : (size_t)0, need);
+        if ((uintptr_t)work % 256 != 0) return fail(ctx, FEM_E_ARG, "build_sparsity: work is not 256-byte aligned");
+        return sparsity_passes(ctx, rmap, cmap, sp, SparsityScratch(work, ncells, rmap->arity, nrows));
+    }
+    DevBuf buf(ctx);
+    HIPC(buf.alloc(need), "alloc");
+    return sparsity_passes(ctx, rmap, cmap, sp, SparsityScratch(buf.p, ncells, rmap->arity, nrows));
 }
 
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
@@ -364,7 +468,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     if (!femk::limits(dim, deg, is_mat, &lim))
         return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: no kernel for this cell/degree");
     hipStream_t s = ctx->stream;
-    DevBuf flag(s), ptr(s), ent(s), tmp(s);
+    DevBuf flag(ctx), ptr(ctx), ent(ctx), tmp(ctx), scan(ctx);
     HIPC(flag.alloc(sizeof(int)), "alloc");
     st = range_check(ctx, args->cell_node, flag.as<int>(), "cell_node");
     if (st != FEM_OK) return st;
@@ -373,8 +477,9 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     HIPC(ptr.alloc(sizeof(int64_t) * (nrows + 1)), "alloc");
     HIPC(ent.alloc(sizeof(int32_t) * (ncells * nl)), "alloc");
     HIPC(tmp.alloc(sizeof(int32_t) * (nrows + 1)), "alloc");
+    HIPC(scan.alloc(sizeof(int64_t) * femk::scan_scratch(nrows)), "alloc");
     HIPC(femk::build_incidence(args->cell_node->values, ncells, nl, nrows, ptr.as<int64_t>(),
-                               ent.as<int32_t>(), tmp.as<int32_t>(), s),
+                               ent.as<int32_t>(), tmp.as<int32_t>(), scan.as<int64_t>(), s),
          "incidence");
     std::vector<int64_t> hptr(nrows + 1);
     std::vector<int32_t> hent(ncells * nl);
@@ -645,23 +750,27 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     p->cell_visits = (int64_t)bcell.size();
     for (int32_t i = 0; i < b; ++i) p->max_blk_cells = std::max(p->max_blk_cells, blk_cptr[i + 1] - blk_cptr[i]);
     p->cell_node = args->cell_node->values;
+    p->cell_vertex = args->cell_vertex->values;
+    p->cn_version = args->cell_node->version;
+    p->cv_version = args->cell_vertex->version;
     p->row_ptr = is_mat ? sp->row_ptr : nullptr;
+    p->mem = ctx->mem;
     std::vector<int32_t> bverts(bcell.size() * (dim + 1));
     for (size_t i = 0; i < bcell.size(); ++i)
         for (int m = 0; m <= dim; ++m) bverts[i * (dim + 1) + m] = hcv[(int64_t)bcell[i] * (dim + 1) + m];
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = upload(&p->blk_row0, blk_row0, &p->bytes, s);
-    if (e == hipSuccess) e = upload(&p->blk_cptr, blk_cptr, &p->bytes, s);
-    if (e == hipSuccess) e = upload(&p->bcell, bcell, &p->bytes, s);
-    if (e == hipSuccess) e = upload(&p->bverts, bverts, &p->bytes, s);
+    if (e == hipSuccess) e = upload(p->mem, &p->blk_row0, blk_row0, &p->bytes, s);
+    if (e == hipSuccess) e = upload(p->mem, &p->blk_cptr, blk_cptr, &p->bytes, s);
+    if (e == hipSuccess) e = upload(p->mem, &p->bcell, bcell, &p->bytes, s);
+    if (e == hipSuccess) e = upload(p->mem, &p->bverts, bverts, &p->bytes, s);
     if (!is_mat) {
         const size_t rb = sizeof(double) * (size_t)femk::reduce_partials(ncells);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->red_partial, rb ? rb : 8);
+        if (e == hipSuccess) e = femk::mem_alloc(p->mem, s, false, rb ? rb : 8, (void **)&p->red_partial);
         if (e == hipSuccess) p->bytes += rb;
         std::vector<int32_t> inc32(nrows + 1);
         for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
-        if (e == hipSuccess) e = upload(&p->inc_ptr, inc32, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->ent, hent16, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->inc_ptr, inc32, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->ent, hent16, &p->bytes, s);
     } else {
         p->nchunks = nchunks;
         p->stream_entries = (int64_t)stream.size();
@@ -680,10 +789,10 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
             hd[5] = (blk_w[i + 1] - blk_w[i]) / NW;
             hd[6] = blk_w[i];
         }
-        if (e == hipSuccess) e = upload(&p->blk_hdr, hdr, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->blk_w, blk_w, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->wq, wq, &p->bytes, s);
-        if (e == hipSuccess) e = upload(&p->pstream, stream, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->blk_hdr, hdr, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->blk_w, blk_w, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->wq, wq, &p->bytes, s);
+        if (e == hipSuccess) e = upload(p->mem, &p->pstream, stream, &p->bytes, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -720,9 +829,12 @@ static fem_status check_plan(fem_ctx *ctx, const fem_plan *plan, const fem_form 
                                              : "a Dat plan (built without a sparsity) is required");
     if (plan->dim != (int)form->cell || plan->degree != form->degree)
         return fail(ctx, FEM_E_ARG, "plan was built for another cell/degree");
-    if (plan->cell_node != args->cell_node->values || plan->ncells != args->cells->size ||
-        plan->nrows != args->cell_node->to->size || plan->nverts != args->cell_vertex->to->size)
+    if (plan->cell_node != args->cell_node->values || plan->cell_vertex != args->cell_vertex->values ||
+        plan->ncells != args->cells->size || plan->nrows != args->cell_node->to->size ||
+        plan->nverts != args->cell_vertex->to->size)
         return fail(ctx, FEM_E_ARG, "plan was built for other Maps");
+    if (plan->cn_version != args->cell_node->version || plan->cv_version != args->cell_vertex->version)
+        return fail(ctx, FEM_E_ARG, "plan was built for another version of its Maps (rebuild the plan)");
     return FEM_OK;
 }
 
@@ -974,7 +1086,7 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
     const int dim = (int)form->cell, deg = form->degree, nl = nloc_of(dim, deg), nv = dim + 1;
     const int64_t ncells = args->cells->size, nverts = args->cell_vertex->to->size,
                   nnodes = args->cell_node->to->size;
-    DevBuf flag(ctx->stream);
+    DevBuf flag(ctx);
     HIPC(flag.alloc(sizeof(int)), "alloc");
     if ((st = range_check(ctx, args->cell_vertex, flag.as<int>(), "cell_vertex")) != FEM_OK) return st;
     if ((st = range_check(ctx, args->cell_node, flag.as<int>(), "cell_node")) != FEM_OK) return st;

@@ -370,10 +370,10 @@ bool edat_ok(const fem_dat *d, const fem_set *set, int dim)
 int upper_pair(int i, int j) { return i * NL - i * (i - 1) / 2 + (j - i); }
 
 template <typename T>
-hipError_t put(T **dst, const std::vector<T> &src, size_t *bytes, hipStream_t s)
+hipError_t put(const fem_mem &m, T **dst, const std::vector<T> &src, size_t *bytes, hipStream_t s)
 {
     const size_t n = src.size() * sizeof(T);
-    hipError_t e = hipMalloc((void **)dst, n ? n : 8);
+    hipError_t e = mem_alloc(m, s, false, n ? n : 8, (void **)dst);
     if (e != hipSuccess) return e;
     *bytes += n;
     return n ? hipMemcpyAsync(*dst, src.data(), n, hipMemcpyHostToDevice, s) : hipSuccess;
@@ -412,17 +412,20 @@ fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args 
     hipStream_t s = ctx->stream;
     // Map range checks on the device (every entry is read once)
     int *dflag = nullptr, hflag = 0;
-    EHIP(hipMalloc(&dflag, sizeof(int)), "alloc");
+    EHIP(mem_alloc(ctx->mem, s, true, sizeof(int), (void **)&dflag), "alloc");
     const fem_map *maps[3] = {args->cell_node, args->cell_vertex, args->cell_coord};
     for (const fem_map *m : maps) {
-        hipError_t e = hipMemsetAsync(dflag, 0, sizeof(int), s);
+        hipError_t e = fill_i32(dflag, 1, 0, s);
         if (e == hipSuccess) e = check_range(m->values, m->from->size * (int64_t)m->arity, m->to->size, dflag, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { (void)hipFree(dflag); return ehip(ctx, e, "range check"); }
-        if (hflag) { (void)hipFree(dflag); return efail(ctx, FEM_E_RANGE, "elasticity plan: a Map entry lies outside its target Set"); }
+        if (e != hipSuccess) { mem_free(ctx->mem, s, true, dflag); return ehip(ctx, e, "range check"); }
+        if (hflag) {
+            mem_free(ctx->mem, s, true, dflag);
+            return efail(ctx, FEM_E_RANGE, "elasticity plan: a Map entry lies outside its target Set");
+        }
     }
-    (void)hipFree(dflag);
+    mem_free(ctx->mem, s, true, dflag);
     std::vector<int32_t> cn((size_t)C * NL);
     std::vector<int64_t> rp3(R + 1);
     std::vector<int32_t> ci3((size_t)sp->nnz);
@@ -507,14 +510,16 @@ fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args 
     p->nblk = 0;
     p->cell_visits = C;
     p->cell_node = args->cell_node->values;
+    p->cn_version = args->cell_node->version;
     p->row_ptr = sp->row_ptr;
     p->e_nslots = ns;
     p->e_prec = (int)form->prec;
-    hipError_t e = put(&p->e_slot_ptr, sptr, &p->bytes, s);
-    if (e == hipSuccess) e = put(&p->e_ent, ent, &p->bytes, s);
-    if (e == hipSuccess) e = put(&p->e_grow, grow, &p->bytes, s);
+    p->mem = ctx->mem;
+    hipError_t e = put(p->mem, &p->e_slot_ptr, sptr, &p->bytes, s);
+    if (e == hipSuccess) e = put(p->mem, &p->e_ent, ent, &p->bytes, s);
+    if (e == hipSuccess) e = put(p->mem, &p->e_grow, grow, &p->bytes, s);
     const size_t wbytes = (size_t)C * BLK * (form->prec == FEM_FP64 ? 8 : 4);
-    if (e == hipSuccess) e = hipMalloc(&p->e_work, wbytes ? wbytes : 8);
+    if (e == hipSuccess) e = mem_alloc(p->mem, s, false, wbytes ? wbytes : 8, &p->e_work);
     if (e == hipSuccess) p->bytes += wbytes;
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -535,6 +540,8 @@ fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *fo
     if (plan->cell_node != args->cell_node->values || plan->ncells != args->cells->size ||
         plan->nrows != args->cell_node->to->size || plan->nverts != args->cell_vertex->to->size)
         return efail(ctx, FEM_E_ARG, "plan was built for other Maps");
+    if (plan->cn_version != args->cell_node->version)
+        return efail(ctx, FEM_E_ARG, "plan was built for another version of its Maps (rebuild the plan)");
     if (!A || !A->sp || (!A->values && plan->nnz > 0)) return efail(ctx, FEM_E_ARG, "assemble_mat: Mat without values");
     if (A->sp->row_ptr != plan->row_ptr || A->sp->nnz != plan->nnz)
         return efail(ctx, FEM_E_ARG, "assemble_mat: Mat sparsity differs from the plan's");

@@ -133,33 +133,41 @@ fem_status fem_facet_plan_create(fem_ctx *ctx, const fem_form *form, const fem_f
     const int64_t nf = fa->facets->size, nrows = fa->facet_node->to->size;
     hipStream_t s = ctx->stream;
     int *flag = nullptr, hflag = 0;
-    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) return ffail(ctx, FEM_E_NOMEM, "facet_plan_create: alloc");
+    if (mem_alloc(ctx->mem, s, true, sizeof(int), (void **)&flag) != hipSuccess)
+        return ffail(ctx, FEM_E_NOMEM, "facet_plan_create: alloc");
     for (const fem_map *m : {fa->facet_vertex, fa->facet_node}) {
-        hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+        hipError_t e = fill_i32(flag, 1, 0, s);
         if (e == hipSuccess) e = check_range(m->values, m->from->size * (int64_t)m->arity, m->to->size, flag, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess || hflag) {
-            (void)hipFree(flag);
+            mem_free(ctx->mem, s, true, flag);
             return e != hipSuccess ? fhip(ctx, e, "range check")
                                    : ffail(ctx, FEM_E_RANGE, "facet_plan_create: a Map entry lies outside its target Set");
         }
     }
-    (void)hipFree(flag);
+    mem_free(ctx->mem, s, true, flag);
     fem_plan *p = new (std::nothrow) fem_plan;
     if (!p) return ffail(ctx, FEM_E_NOMEM, "facet_plan_create: host allocation");
     p->is_mat = 3;
     p->dim = d; p->degree = form->degree; p->nloc = nl;
     p->ncells = nf; p->nrows = nrows; p->nverts = fa->facet_vertex->to->size;
     p->cell_node = fa->facet_node->values;
+    p->cell_vertex = fa->facet_vertex->values;
+    p->cn_version = fa->facet_node->version;
+    p->cv_version = fa->facet_vertex->version;
+    p->mem = ctx->mem;
     int32_t *tmp = nullptr;
-    hipError_t e = hipMalloc((void **)&p->f_ptr, sizeof(int64_t) * (nrows + 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&p->f_ent, sizeof(int32_t) * (nf * nl ? nf * nl : 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&p->f_work, sizeof(double) * (nf * nl ? nf * nl : 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&tmp, sizeof(int32_t) * (nrows + 1));
-    if (e == hipSuccess) e = build_incidence(fa->facet_node->values, nf, nl, nrows, p->f_ptr, p->f_ent, tmp, s);
+    int64_t *scan = nullptr;
+    hipError_t e = mem_alloc(p->mem, s, false, sizeof(int64_t) * (nrows + 1), (void **)&p->f_ptr);
+    if (e == hipSuccess) e = mem_alloc(p->mem, s, false, sizeof(int32_t) * (nf * nl ? nf * nl : 1), (void **)&p->f_ent);
+    if (e == hipSuccess) e = mem_alloc(p->mem, s, false, sizeof(double) * (nf * nl ? nf * nl : 1), (void **)&p->f_work);
+    if (e == hipSuccess) e = mem_alloc(ctx->mem, s, true, sizeof(int32_t) * (nrows + 1), (void **)&tmp);
+    if (e == hipSuccess) e = mem_alloc(ctx->mem, s, true, sizeof(int64_t) * scan_scratch(nrows), (void **)&scan);
+    if (e == hipSuccess) e = build_incidence(fa->facet_node->values, nf, nl, nrows, p->f_ptr, p->f_ent, tmp, scan, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (tmp) (void)hipFree(tmp);
+    mem_free(ctx->mem, s, true, tmp);
+    mem_free(ctx->mem, s, true, scan);
     if (e != hipSuccess) {
         fem_plan_destroy(p);
         return fhip(ctx, e, "facet_plan_create");
@@ -181,6 +189,8 @@ fem_status fem_par_loop_assemble_facets(fem_ctx *ctx, const fem_plan *plan, cons
         plan->cell_node != fa->facet_node->values || plan->ncells != fa->facets->size ||
         plan->nrows != fa->facet_node->to->size)
         return ffail(ctx, FEM_E_ARG, "assemble_facets: the plan was built for other facets");
+    if (plan->cn_version != fa->facet_node->version)
+        return ffail(ctx, FEM_E_ARG, "assemble_facets: the plan was built for another version of its Maps");
     if (!b || !b->set || b->dim != 1 || b->set->size != plan->nrows || (!b->data && plan->nrows > 0))
         return ffail(ctx, FEM_E_ARG, "assemble_facets: b must be a Dat on facet_node's target Set");
     if (acc != FEM_WRITE && acc != FEM_INC) return ffail(ctx, FEM_E_ARG, "output access must be WRITE or INC");

@@ -7,10 +7,20 @@
 
 #include "fem.h"
 
+// Where a context's device memory comes from (fem_ctx_set_allocator): the
+// caller's allocator, or the HIP runtime (hipMalloc for what a plan holds,
+// stream-ordered hipMallocAsync on the context stream for temporaries).
+struct fem_mem {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*release)(void *, void *) = nullptr;
+    void *user = nullptr;
+};
+
 struct fem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cus = 256;
+    fem_mem mem;
     std::string err;
 };
 
@@ -64,6 +74,7 @@ struct fem_plan {
     int64_t e_nslots = 0;
     int e_prec = 0;
     size_t bytes = 0;            // device bytes held
+    fem_mem mem;                 // allocator the arrays below came from
     // device arrays (owned)
     int32_t *blk_row0 = nullptr;  // [nblk+1] first row of each block
     int32_t *blk_cptr = nullptr;  // [nblk+1] offsets into bcell
@@ -75,8 +86,10 @@ struct fem_plan {
     int32_t *blk_w = nullptr;     // Mat plans: [nblk+1] first (chunk, wave) stream of each block
     int32_t *wq = nullptr;        // Mat plans: [streams+1] first batch of each (chunk, wave) stream
     uint16_t *pstream = nullptr;  // Mat plans: the streams
-    // identity of what the plan was built for
+    // identity of what the plan was built for: the Maps' arrays and versions
     const int32_t *cell_node = nullptr;
+    const int32_t *cell_vertex = nullptr;
+    uint64_t cn_version = 0, cv_version = 0;
     const int64_t *row_ptr = nullptr;
 };
 
@@ -92,17 +105,30 @@ namespace femk {
 constexpr int MAT_BATCH = FEM_MAT_BATCH;
 static_assert(MAT_BATCH == 4 || MAT_BATCH == 8, "Mat stream batch width");
 
+// ---- device memory (fem_api.cpp) ----
+// Persistent (plan) or temporary (freed before the call returns, stream-
+// ordered on s) device memory from m; release with the same m, s and temp.
+hipError_t mem_alloc(const fem_mem &m, hipStream_t s, bool temp, size_t bytes, void **p);
+void mem_free(const fem_mem &m, hipStream_t s, bool temp, void *p);
+
 // ---- incidence and sparsity (fem_sparsity.hip) ----
 hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hipStream_t s);
+// Fills n int32 with value (a kernel, not a memset node).
+hipError_t fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
+// int64 elements of scratch an exclusive scan of n values needs.
+int64_t scan_scratch(int64_t n);
 // Row -> incidence: ptr (int64 [nrows+1]) and ent (int32 entry ids c*nloc+l,
-// ascending within each row).  tmp must hold nrows+1 int32.
+// ascending within each row).  tmp must hold nrows+1 int32, scan
+// scan_scratch(nrows) int64.
 hipError_t build_incidence(const int32_t *map, int64_t ncells, int nloc, int64_t nrows,
-                           int64_t *ptr, int32_t *ent, int32_t *tmp, hipStream_t s);
+                           int64_t *ptr, int32_t *ent, int32_t *tmp, int64_t *scan, hipStream_t s);
 // Unique column counts per row (count pass) or columns (fill pass).
 hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_r,
                        const int32_t *cmap, int nloc_c, int64_t nrows, int32_t *counts,
                        const int64_t *row_ptr, int32_t *col_idx, int *overflow, hipStream_t s);
-hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] the total); scan
+// holds scan_scratch(n) int64.
+hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, int64_t *scan, hipStream_t s);
 hipError_t i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- assembly kernels (fem_assemble.hip) ----

@@ -149,9 +149,11 @@ static double req_work(const Model &m, int op)
     return (double)p.cell_visits * nl * nl + (op == FEM_REQ_ASSEMBLE ? (double)m.nnz : 0.0);
 }
 
+// Arena bytes of a request's outputs, each range rounded as the arena carves it.
 static int64_t req_bytes(const Model &m, int op)
 {
-    return op == FEM_REQ_ASSEMBLE ? 8 * (m.nnz + m.nrows) : 8 * m.nrows;
+    return Arena::round(8 * m.nrows ? 8 * m.nrows : 1) +
+           (op == FEM_REQ_ASSEMBLE ? Arena::round(8 * m.nnz ? 8 * m.nnz : 1) : 0);
 }
 
 extern "C" {
@@ -188,12 +190,12 @@ void fem_server_destroy(fem_server *s)
 {
     if (!s) return;
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-    if (s->arena.base) (void)hipFree(s->arena.base);
+    if (s->arena.base) femk::mem_free(s->ctx->mem, nullptr, false, s->arena.base);
     for (Model *m : s->models) {
         fem_plan_destroy(m->mplan);
         fem_plan_destroy(m->vplan);
-        if (m->sp.row_ptr) (void)hipFree(m->sp.row_ptr);
-        if (m->sp.col_idx) (void)hipFree(m->sp.col_idx);
+        femk::mem_free(s->ctx->mem, nullptr, false, m->sp.row_ptr);
+        femk::mem_free(s->ctx->mem, nullptr, false, m->sp.col_idx);
         delete m;
     }
     for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
@@ -239,18 +241,20 @@ fem_status fem_server_add_model(fem_server *s, const fem_form *form, const fem_a
     auto bail = [&](fem_status st) {
         fem_plan_destroy(m->mplan);
         fem_plan_destroy(m->vplan);
-        if (m->sp.row_ptr) (void)hipFree(m->sp.row_ptr);
-        if (m->sp.col_idx) (void)hipFree(m->sp.col_idx);
+        femk::mem_free(ctx->mem, nullptr, false, m->sp.row_ptr);
+        femk::mem_free(ctx->mem, nullptr, false, m->sp.col_idx);
         delete m;
         return st;
     };
-    hipError_t e = hipMalloc(&m->sp.row_ptr, sizeof(int64_t) * (m->nrows + 1));
+    hipError_t e = femk::mem_alloc(ctx->mem, ctx->stream, false, sizeof(int64_t) * (m->nrows + 1),
+                                   (void **)&m->sp.row_ptr);
     if (e != hipSuccess) return bail(shed(ctx, e, "add_model: alloc"));
-    fem_status st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp);
+    fem_status st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp, nullptr, nullptr);
     if (st != FEM_OK) return bail(st);
-    e = hipMalloc(&m->sp.col_idx, sizeof(int32_t) * (m->sp.nnz ? m->sp.nnz : 1));
+    e = femk::mem_alloc(ctx->mem, ctx->stream, false, sizeof(int32_t) * (m->sp.nnz ? m->sp.nnz : 1),
+                        (void **)&m->sp.col_idx);
     if (e != hipSuccess) return bail(shed(ctx, e, "add_model: alloc"));
-    if ((st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp)) != FEM_OK) return bail(st);
+    if ((st = fem_build_sparsity(ctx, &m->cn, &m->cn, &m->sp, nullptr, nullptr)) != FEM_OK) return bail(st);
     if ((st = fem_plan_create(ctx, &m->form, &m->args, &m->sp, &m->mplan)) != FEM_OK) return bail(st);
     if ((st = fem_plan_create(ctx, &m->form, &m->args, nullptr, &m->vplan)) != FEM_OK) return bail(st);
     m->nnz = m->sp.nnz;
@@ -273,7 +277,7 @@ fem_status fem_server_submit(fem_server *s, int32_t model, int32_t op, const dou
     if (op != FEM_REQ_ASSEMBLE && op != FEM_REQ_ACTION) return sfail(ctx, FEM_E_ARG, "submit: unknown operation");
     if (op == FEM_REQ_ACTION && !x && s->models[model]->nrows > 0) return sfail(ctx, FEM_E_ARG, "submit: action needs x");
     const int64_t bytes = req_bytes(*s->models[model], op);
-    if (s->resident + bytes > s->budget)
+    if (bytes > (s->budget - s->resident) / 256 * 256)   // the output arena's size
         return sfail(ctx, FEM_E_NOMEM, "submit: the request's outputs can never fit the HBM budget");
     Request r;
     r.model = model; r.op = op; r.x = x; r.t_arrival = arrival_time; r.bytes = bytes;
@@ -306,7 +310,7 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
     // the output arena: everything the resident models leave of the budget
     if (!s->arena.base && !s->queue.empty()) {
         const int64_t size = (s->budget - s->resident) / 256 * 256;
-        SHIP(hipMalloc((void **)&s->arena.base, size), "poll: output arena");
+        SHIP(femk::mem_alloc(ctx->mem, ctx->stream, false, size, (void **)&s->arena.base), "poll: output arena");
         s->arena.size = size;
         s->arena.free_[0] = size;
     }

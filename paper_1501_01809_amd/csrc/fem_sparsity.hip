@@ -27,6 +27,13 @@ __global__ void k_check_range(const int32_t *__restrict__ v, int64_t n, int64_t 
     }
 }
 
+__global__ void k_fill_value(int32_t *__restrict__ p, int64_t n, int32_t value)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
 __global__ void k_count(const int32_t *__restrict__ map, int64_t n, int32_t *__restrict__ cnt)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -208,31 +215,35 @@ hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hi
     return hipGetLastError();
 }
 
-hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, hipStream_t s)
+int64_t scan_scratch(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_value, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan(const int32_t *in, int64_t *out, int64_t n, int64_t *tile_sum, hipStream_t s)
 {
     const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    int64_t *tile_sum = nullptr;
-    hipError_t e = hipMallocAsync((void **)&tile_sum, sizeof(int64_t) * (ntiles + 1), s);
-    if (e != hipSuccess) return e;
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(SCAN_T), 0, s, in, n, tile_sum);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, tile_sum, ntiles, out + n);
     if (ntiles > 0)
         hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(SCAN_T), 0, s, in, n, tile_sum, out);
-    e = hipGetLastError();
-    hipError_t e2 = hipFreeAsync(tile_sum, s);
-    return e != hipSuccess ? e : e2;
+    return hipGetLastError();
 }
 
 hipError_t build_incidence(const int32_t *map, int64_t ncells, int nloc, int64_t nrows,
-                           int64_t *ptr, int32_t *ent, int32_t *tmp, hipStream_t s)
+                           int64_t *ptr, int32_t *ent, int32_t *tmp, int64_t *scan, hipStream_t s)
 {
     const int64_t n = ncells * nloc;
-    hipError_t e = hipMemsetAsync(tmp, 0, sizeof(int32_t) * (nrows + 1), s);
+    hipError_t e = fill_i32(tmp, nrows + 1, 0, s);
     if (e != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_count, dim3(grid_for(n, 256)), dim3(256), 0, s, map, n, tmp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = exclusive_scan(tmp, ptr, nrows, s)) != hipSuccess) return e;
+    if ((e = exclusive_scan(tmp, ptr, nrows, scan, s)) != hipSuccess) return e;
     if (nrows > 0)
         hipLaunchKernelGGL(k_i64_to_i32, dim3(grid_for(nrows, 256)), dim3(256), 0, s, ptr, tmp, nrows);
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, map, n, tmp, ent);

@@ -41,7 +41,7 @@ class fem_set(C.Structure):
 
 class fem_map(C.Structure):
     _fields_ = [("from_", C.POINTER(fem_set)), ("to", C.POINTER(fem_set)),
-                ("arity", C.c_int32), ("values", C.c_void_p)]
+                ("arity", C.c_int32), ("values", C.c_void_p), ("version", C.c_uint64)]
 
 
 class fem_dat(C.Structure):
@@ -72,7 +72,7 @@ class fem_block(C.Structure):
 
 class fem_form(C.Structure):
     _fields_ = [("kind", C.c_int), ("cell", C.c_int), ("degree", C.c_int32),
-                ("dim", C.c_int32), ("prec", C.c_int)]
+                ("dim", C.c_int32), ("prec", C.c_int), ("qdegree", C.c_int32)]
 
 
 class fem_args(C.Structure):
@@ -82,7 +82,11 @@ class fem_args(C.Structure):
                 ("cell_coord", C.POINTER(fem_map))]
 
 
-EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_last_error", "fem_sync",
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_ctx_set_allocator", "fem_last_error",
+           "fem_sync",
            "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
@@ -107,9 +111,11 @@ def lib():
         L.fem_ctx_create.argtypes = [C.c_int, P, C.POINTER(P)]
         L.fem_ctx_destroy.argtypes = [P]; L.fem_ctx_destroy.restype = None
         L.fem_ctx_set_stream.argtypes = [P, P]
+        L.fem_ctx_set_allocator.argtypes = [P, ALLOC_FN, RELEASE_FN, P]
         L.fem_last_error.argtypes = [P]; L.fem_last_error.restype = C.c_char_p
         L.fem_sync.argtypes = [P]
-        L.fem_build_sparsity.argtypes = [P, C.POINTER(fem_map), C.POINTER(fem_map), C.POINTER(fem_sparsity)]
+        L.fem_build_sparsity.argtypes = [P, C.POINTER(fem_map), C.POINTER(fem_map), C.POINTER(fem_sparsity), P,
+                                         C.POINTER(C.c_size_t)]
         L.fem_plan_create.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_sparsity),
                                       C.POINTER(P)]
         L.fem_plan_destroy.argtypes = [P]; L.fem_plan_destroy.restype = None
@@ -159,18 +165,51 @@ def _ptr(t):
 
 
 class Context:
-    """fem_ctx bound to a device and to torch's current stream on it."""
+    """fem_ctx bound to a device and to torch's current stream on it.  With
+    torch_memory (the default) the library's device memory (plans, setup
+    temporaries) comes from torch's caching allocator on that stream, so it
+    is visible to torch and reused by it; otherwise from the HIP runtime."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, torch_memory: bool = True):
         import torch
         L = lib()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
+        self.stream = stream
         self.h = C.c_void_p()
         st = L.fem_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(self.h))
         if st != FEM_OK:
             raise FemError(st, "fem_ctx_create failed")
+        self._alloc = self._release = None
+        self._callbacks = []   # every allocator installed: plans keep calling theirs
+        if torch_memory:
+            self.set_allocator(*torch_allocator(device, stream))
+
+    def set_allocator(self, alloc, release):
+        """alloc(nbytes) -> device address (int, 0 on failure) and
+        release(address); both None restore the HIP runtime.  The callables
+        are kept alive by the context."""
+        if alloc is None:
+            self._alloc = self._release = None
+            self.check(lib().fem_ctx_set_allocator(self.h, ALLOC_FN(), RELEASE_FN(), None))
+            return
+
+        def _a(n, user):
+            try:
+                return alloc(n) or None
+            except Exception:
+                return None
+
+        def _r(p, user):
+            try:
+                release(p)
+            except Exception:
+                pass
+
+        self._alloc, self._release = ALLOC_FN(_a), RELEASE_FN(_r)
+        self._callbacks.append((self._alloc, self._release))
+        self.check(lib().fem_ctx_set_allocator(self.h, self._alloc, self._release, None))
 
     def check(self, st):
         if st != FEM_OK:
@@ -191,8 +230,23 @@ class Context:
             pass
 
 
-def form(kind="helmholtz", cell=3, degree=1, dim=1, prec=FEM_FP64):
-    return fem_form(KINDS.get(kind, kind) if isinstance(kind, str) else kind, cell, degree, dim, prec)
+def torch_allocator(device: int, stream):
+    """(alloc, release) callables over torch's caching allocator on `stream`."""
+    import torch
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(max(int(n), 1), device, stream)
+
+    def release(p):
+        torch.cuda.caching_allocator_delete(p)
+
+    return alloc, release
+
+
+def form(kind="helmholtz", cell=3, degree=1, dim=1, prec=FEM_FP64, qdegree=0):
+    """qdegree 0: exact integration (any degree at least the integrand's is
+    the same); a lower positive degree is refused by the library."""
+    return fem_form(KINDS.get(kind, kind) if isinstance(kind, str) else kind, cell, degree, dim, prec, qdegree)
 
 
 class Args:
@@ -236,6 +290,14 @@ class Args:
         if cell_coord is not None:
             self.c.cell_coord = C.pointer(self.cc)
 
+    def set_versions(self, cell_vertex=None, cell_node=None):
+        """Declare that a Map's contents were rewritten in place (its version,
+        fem_map.version): plans built at the older version are then refused."""
+        if cell_vertex is not None:
+            self.cv.version = cell_vertex
+        if cell_node is not None:
+            self.cn.version = cell_node
+
     def with_coeffs(self, *coeffs, nodal=False):
         return Args(self.cell_vertex, self.coords, self.cell_node, self.nodes.size, coeffs, nodal,
                     self.cell_coord)
@@ -265,8 +327,12 @@ class Plan:
             pass
 
 
-def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | None = None) -> Sparsity:
-    """Two-pass CSR sparsity (count, then fill) of the Mat through rmap/cmap."""
+def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | None = None,
+                       work=None) -> Sparsity:
+    """Two-pass CSR sparsity (count, then fill) of the Mat through rmap/cmap.
+    work="torch": query the scratch size and pass a torch buffer of it (the
+    library then allocates nothing); None: the library takes its scratch
+    from the context's allocator."""
     import torch
     cmap = rmap if cmap is None else cmap
     ncols = nrows if ncols is None else ncols
@@ -275,10 +341,19 @@ def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | N
     cm = fem_map(C.pointer(cells), C.pointer(cs), cmap.shape[1], _ptr(cmap))
     row_ptr = torch.empty(nrows + 1, dtype=torch.int64, device=rmap.device)
     sp = fem_sparsity(0, 0, 0, _ptr(row_ptr), None)
-    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp)))
+    if work == "torch":
+        need = C.c_size_t(0)
+        ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp), None, C.byref(need)))
+        buf = torch.empty(max(need.value, 1), dtype=torch.uint8, device=rmap.device)
+        wp, wb = C.c_void_p(buf.data_ptr()), C.byref(need)
+    else:
+        buf, wp, wb = None, None, None
+    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp), wp, wb))
     col_idx = torch.empty(max(sp.nnz, 1), dtype=torch.int32, device=rmap.device)
     sp.col_idx = C.c_void_p(col_idx.data_ptr())
-    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp)))
+    ctx.check(lib().fem_build_sparsity(ctx.h, C.byref(rm), C.byref(cm), C.byref(sp), wp, wb))
+    if buf is not None:
+        buf.record_stream(ctx.stream)   # in use until the queued fill pass has run
     return Sparsity(row_ptr, col_idx[:sp.nnz], nrows, ncols)
 
 
@@ -298,7 +373,7 @@ def fem_plan_create(ctx: Context, frm: fem_form, args: Args, sp: Sparsity | None
     h = C.c_void_p()
     ctx.check(lib().fem_plan_create(ctx.h, C.byref(frm), C.byref(args.c),
                                     C.byref(sp.c) if sp is not None else None, C.byref(h)))
-    return Plan(h, (args, sp))
+    return Plan(h, (args, sp, ctx))   # the plan releases its memory through ctx's allocator
 
 
 def fem_par_loop_assemble_mat(ctx: Context, plan: Plan, frm: fem_form, args: Args, values, sp: Sparsity,
@@ -380,7 +455,7 @@ class Facets:
 def fem_facet_plan_create(ctx: Context, frm: fem_form, fa: Facets) -> Plan:
     h = C.c_void_p()
     ctx.check(lib().fem_facet_plan_create(ctx.h, C.byref(frm), C.byref(fa.c), C.byref(h)))
-    return Plan(h, (fa,))
+    return Plan(h, (fa, ctx))
 
 
 def fem_par_loop_assemble_facets(ctx: Context, plan: Plan, frm: fem_form, fa: Facets, b, acc: int = FEM_WRITE):

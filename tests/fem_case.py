@@ -54,14 +54,27 @@ def make_case(kind: str, n: int, degree: int, seed: int = 1501, jitter: float = 
                 np.ascontiguousarray(cn, dtype=np.int32), N, kappa, f, x)
 
 
-def check_close(got, ref, absref, what=""):
+def check_close(got, ref, absref, what="", cabs=None):
+    """FP64 bar: |got - ref| <= TOL * S per entry, S the oracle's term-level
+    scale, and the relative Frobenius error <= TOL.  With cabs (the
+    contribution-level scale, sum over cells of |element entry|, which the
+    term-level scale can exceed on near-cancelling entries) the worst error is
+    also reported against it, so that the strength of the bar is visible;
+    returns both worst ratios."""
     got = np.asarray(got); ref = np.asarray(ref); absref = np.asarray(absref)
     err = np.abs(got - ref)
     bad = err > TOL * absref + 1e-300
-    assert not bad.any(), (f"{what}: {bad.sum()} entries outside {TOL}*S; worst "
-                           f"{(err / np.maximum(absref, 1e-300)).max():.3e}")
+    w_term = float((err / np.maximum(absref, 1e-300)).max()) if err.size else 0.0
+    assert not bad.any(), f"{what}: {bad.sum()} entries outside {TOL}*S; worst {w_term:.3e}"
     nref = np.linalg.norm(ref)
     assert np.linalg.norm(got - ref) <= TOL * nref + 1e-300, f"{what}: Frobenius error too large"
+    w_con = None
+    if cabs is not None and err.size:
+        cabs = np.asarray(cabs)
+        w_con = float((err / np.maximum(cabs, 1e-300)).max())
+        print(f"{what}: worst error / term-level S = {w_term:.2e}, / contribution-level S = {w_con:.2e}",
+              flush=True)
+    return w_term, w_con
 
 
 class GpuRun:

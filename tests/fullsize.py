@@ -1,0 +1,103 @@
+"""Full-size GPU runs shared by the full-size parity tests: the bench's
+inputs (seeded lattice mesh, interior jitter 0.2h, seeded shuffle, then the
+library's Hilbert renumbering), the CSR matrix, the source vector and the
+action assembled through the C ABI exactly as the bench launches them, copied
+back to the host."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def assemble_full(mesh: str, n: int, deg: int, seed: int = 1501):
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1501_01809_amd import fem as F
+    dim = 3 if mesh == "cube" else 2
+    print(f"building inputs: {mesh} n={n} P{deg}", flush=True)
+    d = bench.build_inputs(n, deg, seed, mesh)
+    ctx = F.Context(0)
+    dev = "cuda"
+    up = lambda dd: {k: torch.from_numpy(dd[k]).to(dev) for k in ("cells", "coords", "cn", "kappa", "f", "x")}
+    g = up(d)
+    form = F.form("helmholtz", dim, deg)
+    cp, vp, npn = F.fem_renumber(ctx, form, F.Args(g["cells"], g["coords"], g["cn"], d["N"], [g["kappa"]]))
+    for p, size in ((cp, d["cells"].shape[0]), (vp, d["coords"].shape[0]), (npn, d["N"])):
+        assert np.array_equal(np.sort(p), np.arange(size)), "renumbering is not a permutation"
+    d = bench.apply_perms(d, cp, vp, npn)
+    g = up(d)
+    args_k = F.Args(g["cells"], g["coords"], g["cn"], d["N"], [g["kappa"]])
+    args_f = F.Args(g["cells"], g["coords"], g["cn"], d["N"], [g["f"]])
+    print("sparsity + plans", flush=True)
+    sp = F.fem_build_sparsity(ctx, g["cn"], d["N"])
+    mplan = F.fem_plan_create(ctx, form, args_k, sp)
+    vplan = F.fem_plan_create(ctx, form, args_k, None)
+    vals = torch.empty(sp.col_idx.numel(), dtype=torch.float64, device=dev)
+    b = torch.empty(d["N"], dtype=torch.float64, device=dev)
+    y = torch.empty(d["N"], dtype=torch.float64, device=dev)
+    F.fem_par_loop_assemble_mat(ctx, mplan, form, args_k, vals, sp)
+    F.fem_par_loop_assemble_vec(ctx, vplan, F.form("source", dim, deg), args_f, b)
+    F.fem_apply_action(ctx, vplan, form, args_k, g["x"], y)
+    ones = torch.ones(d["N"], dtype=torch.float64, device=dev)
+    y1 = torch.empty_like(y)
+    F.fem_apply_action(ctx, vplan, form, args_k, ones, y1)
+    vals2 = torch.empty_like(vals)
+    F.fem_par_loop_assemble_mat(ctx, mplan, form, args_k, vals2, sp)
+    F.fem_sync(ctx)
+    print(f"assembled: nnz={sp.col_idx.numel()} mat plan {mplan.info()} vec plan {vplan.info()}", flush=True)
+    out = dict(d=d, n=n, deg=deg, dim=dim, rp=sp.row_ptr.cpu().numpy(), ci=sp.col_idx.cpu().numpy(),
+               vals=vals.cpu().numpy(), vals2=vals2.cpu().numpy(), b=b.cpu().numpy(),
+               y=y.cpu().numpy(), y1=y1.cpu().numpy(), mplan=mplan.info(), vplan=vplan.info())
+    del vals, vals2, sp, mplan, vplan
+    torch.cuda.empty_cache()
+    return out
+
+
+def nnz_closed_form(mesh: str, deg: int, n: int) -> int:
+    """Exact nnz of the Lagrange P_deg pattern on the n x n x 2 square or the
+    n^3 x 6 Kuhn cube (integer polynomial fits of the enumeration)."""
+    if mesh == "square":
+        return {1: 7 * n * n + 6 * n + 1, 2: 46 * n * n + 16 * n + 1, 3: 153 * n * n + 30 * n + 1}[deg]
+    return {1: 15 * n ** 3 + 21 * n * n + 9 * n + 1, 2: 230 * n ** 3 + 138 * n * n + 24 * n + 1,
+            3: 1311 * n ** 3 + 459 * n * n + 45 * n + 1}[deg]
+
+
+def check_sampled_rows(full, nsample=48, seed=12):
+    """Rows drawn at random (plus the first and last) against the oracle's
+    row-by-row assembly: columns bit-exact, values, vector and action to the
+    FP64 bar; prints the worst error against both scales."""
+    import oracle
+    from fem_case import check_close
+    d, rp, ci, vals, dim, deg = full["d"], full["rp"], full["ci"], full["vals"], full["dim"], full["deg"]
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([rng.choice(d["N"], nsample, replace=False), [0, d["N"] - 1]]))
+    ref = oracle.mat_rows(dim, deg, d["cells"], d["coords"], d["cn"], d["kappa"], d["N"], rows,
+                          contrib_scale=True)
+    got = np.concatenate([vals[rp[r]:rp[r + 1]] for r in rows])
+    for r, (cols, v, a, ca) in zip(rows, ref):
+        np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], cols)
+    check_close(got, np.concatenate([t[1] for t in ref]), np.concatenate([t[2] for t in ref]),
+                "sampled Mat rows", cabs=np.concatenate([t[3] for t in ref]))
+    bs, ba = oracle.vec_rows(dim, deg, d["cells"], d["coords"], d["cn"], d["f"], d["N"], rows)
+    check_close(full["b"][rows], bs, ba, "vec")
+    ys, ya = oracle.action_rows(dim, deg, d["cells"], d["coords"], d["cn"], d["kappa"], d["x"], d["N"], rows)
+    check_close(full["y"][rows], ys, ya, "action")
+
+
+def check_whole_output(full):
+    """Properties that hold at any size: bitwise run-to-run reproducibility,
+    sum of the Helmholtz matrix = |Omega| = 1 (stiffness rows sum to zero),
+    A 1 = M 1 sums to |Omega|, bitwise symmetry on sampled rows."""
+    vals, rp, ci = full["vals"], full["rp"], full["ci"]
+    assert np.array_equal(vals.view(np.uint64), full["vals2"].view(np.uint64))
+    assert abs(vals.sum() - 1.0) < 1e-9
+    assert abs(full["y1"].sum() - 1.0) < 1e-11
+    rng = np.random.default_rng(5)
+    for r in rng.choice(rp.size - 1, 64, replace=False):
+        for k in range(rp[r], rp[r + 1]):
+            c = ci[k]
+            kk = rp[c] + np.searchsorted(ci[rp[c]:rp[c + 1]], r)
+            assert ci[kk] == r and vals[kk] == vals[k]

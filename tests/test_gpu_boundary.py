@@ -1,0 +1,152 @@
+"""The boundary's memory, versioning and quadrature contract, through the C
+ABI: device memory from the caller's allocator (counted), caller-provided
+sparsity scratch (query, then provide), Map versions that invalidate plans,
+the quadrature degree, and the sparsity's row-length limit as a status code."""
+import numpy as np
+import pytest
+
+import oracle
+from fem_case import GpuRun, check_close, make_case
+
+pytestmark = pytest.mark.gpu
+
+
+class Counting:
+    """An allocator over torch's caching allocator that counts its calls."""
+
+    def __init__(self, device, stream):
+        from paper_1501_01809_amd import fem as F
+        self.a, self.r = F.torch_allocator(device, stream)
+        self.live = {}
+        self.allocs = self.releases = 0
+
+    def alloc(self, n):
+        p = self.a(n)
+        self.live[p] = n
+        self.allocs += 1
+        return p
+
+    def release(self, p):
+        assert p in self.live, "release of memory the allocator did not hand out"
+        del self.live[p]
+        self.releases += 1
+        self.r(p)
+
+
+def test_allocator_callbacks_carry_plan_and_setup_memory():
+    import torch
+    from paper_1501_01809_amd import fem as F
+    c = make_case("cube", 4, 2, shuffle=True)
+    ref = GpuRun(c)
+    ref.ctx = F.Context(0, torch_memory=False)   # the HIP runtime's memory
+    want_mat, want_vec = ref.mat(), ref.vec()
+
+    g = GpuRun(c)
+    cnt = Counting(0, g.ctx.stream)
+    g.ctx.set_allocator(cnt.alloc, cnt.release)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    sp = g.sparsity()
+    assert cnt.allocs > 0 and cnt.releases == cnt.allocs, "sparsity scratch is released before the call returns"
+    n0 = cnt.allocs
+    mplan, vplan = g.mat_plan(), g.vec_plan()
+    held = sum(cnt.live.values())
+    assert cnt.allocs > n0 and held >= mplan.info()["device_bytes"] + vplan.info()["device_bytes"]
+    assert torch.cuda.memory_allocated() - before >= held   # visible to torch
+    got_mat, got_vec = g.mat(), g.vec()
+    assert np.array_equal(got_mat, want_mat) and np.array_equal(got_vec, want_vec)
+    n1 = cnt.allocs
+    g.mat(); g.vec(); g.action()
+    assert cnt.allocs == n1, "assembly calls allocate nothing"
+    g._mplan = g._vplan = None
+    del mplan, vplan
+    import gc
+    gc.collect()
+    assert cnt.releases == cnt.allocs and not cnt.live
+    del sp
+
+
+def test_sparsity_work_buffer_query_then_provide():
+    import ctypes as C
+    import torch
+    from paper_1501_01809_amd import fem as F
+    c = make_case("square", 12, 3, shuffle=True)
+    g = GpuRun(c)
+    rp, ci = oracle.sparsity(c.cell_node, c.nnodes)
+    cnt = Counting(0, g.ctx.stream)
+    g.ctx.set_allocator(cnt.alloc, cnt.release)
+    sp = F.fem_build_sparsity(g.ctx, g.cn, c.nnodes, work="torch")
+    assert cnt.allocs == 0, "with a work buffer the call allocates nothing"
+    assert np.array_equal(sp.row_ptr.cpu().numpy(), rp) and np.array_equal(sp.col_idx.cpu().numpy(), ci)
+    # too small, then misaligned: refused before anything is queued
+    cells = F.fem_set(c.cell_node.shape[0]); rows = F.fem_set(c.nnodes)
+    m = F.fem_map(C.pointer(cells), C.pointer(rows), c.cell_node.shape[1], F._ptr(g.cn), 0)
+    row_ptr = torch.empty(c.nnodes + 1, dtype=torch.int64, device="cuda")
+    s = F.fem_sparsity(0, 0, 0, F._ptr(row_ptr), None)
+    need = C.c_size_t(0)
+    g.ctx.check(F.lib().fem_build_sparsity(g.ctx.h, C.byref(m), C.byref(m), C.byref(s), None, C.byref(need)))
+    assert need.value > 0
+    buf = torch.empty(need.value + 512, dtype=torch.uint8, device="cuda")
+    small = C.c_size_t(need.value - 256)
+    assert F.lib().fem_build_sparsity(g.ctx.h, C.byref(m), C.byref(m), C.byref(s), F._ptr(buf),
+                                      C.byref(small)) == F.FEM_E_ARG
+    odd = C.c_size_t(need.value)
+    assert F.lib().fem_build_sparsity(g.ctx.h, C.byref(m), C.byref(m), C.byref(s),
+                                      C.c_void_p(buf.data_ptr() + 8), C.byref(odd)) == F.FEM_E_ARG
+    F.fem_sync(g.ctx)
+
+
+def test_map_version_invalidates_plans():
+    from paper_1501_01809_amd import fem as F
+    c = make_case("square", 8, 2, shuffle=True)
+    g = GpuRun(c)
+    want = g.mat()
+    # the caller rewrites cell_node in place (here: the same contents) and says so
+    g.args_k.set_versions(cell_node=1)
+    with pytest.raises(F.FemError) as e:
+        g.mat()
+    assert e.value.status == F.FEM_E_ARG and "version" in str(e.value)
+    with pytest.raises(F.FemError) as e:
+        g.action()
+    assert e.value.status == F.FEM_E_ARG
+    g._mplan = g._vplan = None           # rebuilt at the new version
+    assert np.array_equal(g.mat(), want)
+    g.args_k.set_versions(cell_vertex=7)
+    with pytest.raises(F.FemError):
+        g.mat()
+
+
+def test_quadrature_degree():
+    from paper_1501_01809_amd import fem as F
+    c = make_case("cube", 3, 2)
+    g = GpuRun(c)
+    want = g.mat()
+    g.form = F.form("helmholtz", 3, 2, qdegree=6)   # above the integrand's degree 4: exact, the same values
+    g._mplan = None
+    assert np.array_equal(g.mat(), want)
+    with pytest.raises(F.FemError) as e:
+        F.fem_plan_create(g.ctx, F.form("helmholtz", 3, 2, qdegree=2), g.args_k, None)
+    assert e.value.status == F.FEM_E_UNSUPPORTED
+
+
+def test_row_candidate_limit_is_a_status():
+    """A vertex with 700 triangles around it: its row gathers 2100 candidate
+    columns (with repetition), beyond the 2048 a row's LDS holds; the count
+    pass reports FEM_E_UNSUPPORTED instead of a wrong pattern."""
+    import torch
+    from paper_1501_01809_amd import fem as F
+    n = 700
+    t = np.arange(n)
+    tri = np.stack([np.zeros(n, dtype=np.int32), 1 + t, 1 + (t + 1) % n], 1).astype(np.int32)
+    cn = torch.from_numpy(tri).cuda()
+    ctx = F.Context(0)
+    with pytest.raises(F.FemError) as e:
+        F.fem_build_sparsity(ctx, cn, n + 1)
+    assert e.value.status == F.FEM_E_UNSUPPORTED and "2048" in str(e.value)
+    # 600 triangles (1800 candidates) are within the limit and match the oracle
+    m = 600
+    t = np.arange(m)
+    tri = np.stack([np.zeros(m, dtype=np.int32), 1 + t, 1 + (t + 1) % m], 1).astype(np.int32)
+    sp = F.fem_build_sparsity(ctx, torch.from_numpy(tri).cuda(), m + 1)
+    rp, ci = oracle.sparsity(tri, m + 1)
+    assert np.array_equal(sp.row_ptr.cpu().numpy(), rp) and np.array_equal(sp.col_idx.cpu().numpy(), ci)

@@ -158,3 +158,27 @@ def test_sampled_rows_match_full_assembly(kind, n, deg):
     y, _ = oracle.apply_action(m.dim, deg, m.cells, m.coords, cn, kappa, x, N)
     ys, _ = oracle.action_rows(m.dim, deg, m.cells, m.coords, cn, kappa, x, N, rows)
     np.testing.assert_array_equal(ys, y[rows])
+
+
+@pytest.mark.parametrize("kind,n,deg", CASES)
+def test_scales_bracket_the_values(kind, n, deg):
+    """The two rounding scales the oracle returns bracket each entry:
+    |a_ij| <= sum over cells of |element entry| <= sum over cells and points
+    of |term| (triangle inequality, twice).  The P1 mass matrix has only
+    positive element entries (|K|(1 + delta_ij)/((d+1)(d+2))), so there the
+    contribution-level scale is the value itself, bit for bit; mat_rows
+    returns the same scales as the full assembly."""
+    m = _mesh(kind, n)
+    cn, N = fi.node_map(m, deg)
+    kap = np.random.default_rng(3).uniform(0.5, 1.5, m.nverts)
+    rp, ci = oracle.sparsity(cn, N)
+    v, a, ca = oracle.assemble_mat(m.dim, deg, m.cells, m.coords, cn, kap, rp, ci, contrib_scale=True)
+    assert np.all(np.abs(v) <= ca * (1 + 1e-14)) and np.all(ca <= a * (1 + 1e-14))
+    rows = np.array([0, N // 2, N - 1])
+    for r, (cols, vr, ar, car) in zip(rows, oracle.mat_rows(m.dim, deg, m.cells, m.coords, cn, kap, N, rows,
+                                                          contrib_scale=True)):
+        np.testing.assert_array_equal(cols, ci[rp[r]:rp[r + 1]])
+        np.testing.assert_allclose(car, ca[rp[r]:rp[r + 1]], rtol=1e-13)
+    if deg == 1:
+        vm, am, cm = oracle.assemble_mat(m.dim, 1, m.cells, m.coords, cn, kap, rp, ci, "mass", contrib_scale=True)
+        assert np.all(vm > 0) and np.array_equal(vm, cm)
