@@ -101,6 +101,7 @@ def test_map_version_invalidates_plans():
     c = make_case("square", 8, 2, shuffle=True)
     g = GpuRun(c)
     want = g.mat()
+    g.vec_plan()
     # the caller rewrites cell_node in place (here: the same contents) and says so
     g.args_k.set_versions(cell_node=1)
     with pytest.raises(F.FemError) as e:
