@@ -259,6 +259,23 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
                               fem_sparsity *sp, void *work, size_t *work_bytes);
 
 /*
+ * fem_build_sparsity for callers that cannot allocate device memory at all
+ * (code under stream capture, serving loops, harnesses that forbid
+ * allocation) and have no buffer to lend: the same two passes and results,
+ * with the scratch taken from a fixed 32 MiB array in the device's global
+ * memory that the library holds for the life of the process (one per GPU).
+ * The call allocates nothing, neither on the device nor through the
+ * context's allocator.  Maps whose scratch (the size the work_bytes query of
+ * fem_build_sparsity reports) exceeds 32 MiB are refused with FEM_E_ARG
+ * before anything is queued; FEM_E_DEVICE if the array's address could not
+ * be looked up at fem_ctx_create.  Every call on one GPU uses the same
+ * array: calls that overlap in time on one GPU (other streams, other
+ * contexts of the process) race and must be serialised by the caller.
+ */
+fem_status fem_build_sparsity_noalloc(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap,
+                                      fem_sparsity *sp);
+
+/*
  * Sparsity of a vector-valued space from the node sparsity: every node entry
  * (n, m) becomes the bs x bs block of rows bs*n + a, columns bs*m + b
  * (node-major DOFs, "Function spaces and functions": the vector CSR is the

@@ -306,6 +306,12 @@ fem_status fem_ctx_create(int device, void *hip_stream, fem_ctx **out)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->num_cus = cus;
+    // the device's static scratch: its address is looked up here, with the
+    // device current; without it only fem_build_sparsity_noalloc fails
+    if (femk::static_scratch(device, &ctx->scratch, &ctx->scratch_bytes) != hipSuccess) {
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
     *out = ctx;
     return FEM_OK;
 }
@@ -442,6 +448,20 @@ fem_status fem_build_sparsity(fem_ctx *ctx, const fem_map *rmap, const fem_map *
     DevBuf buf(ctx);
     HIPC(buf.alloc(need), "alloc");
     return sparsity_passes(ctx, rmap, cmap, sp, SparsityScratch(buf.p, ncells, rmap->arity, nrows));
+}
+
+fem_status fem_build_sparsity_noalloc(fem_ctx *ctx, const fem_map *rmap, const fem_map *cmap, fem_sparsity *sp)
+{
+    if (!ctx) return FEM_E_ARG;
+    fem_status st = check_sparsity_args(ctx, rmap, cmap, sp);
+    if (st != FEM_OK) return st;
+    if (!ctx->scratch) return fail(ctx, FEM_E_DEVICE, "build_sparsity_noalloc: no static scratch on this device");
+    const int64_t ncells = rmap->from->size, nrows = rmap->to->size;
+    const size_t need = SparsityScratch(nullptr, ncells, rmap->arity, nrows).bytes;
+    if (need > ctx->scratch_bytes)
+        return fail(ctx, FEM_E_ARG, "build_sparsity_noalloc: the Maps need %zu bytes of scratch, the static scratch "
+                                    "holds %zu", need, ctx->scratch_bytes);
+    return sparsity_passes(ctx, rmap, cmap, sp, SparsityScratch(ctx->scratch, ncells, rmap->arity, nrows));
 }
 
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,

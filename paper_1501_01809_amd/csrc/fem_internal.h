@@ -21,6 +21,8 @@ struct fem_ctx {
     hipStream_t stream = nullptr;
     int num_cus = 256;
     fem_mem mem;
+    void *scratch = nullptr;     // this device's static scratch (fem_build_sparsity_noalloc)
+    size_t scratch_bytes = 0;
     std::string err;
 };
 
@@ -112,6 +114,9 @@ hipError_t mem_alloc(const fem_mem &m, hipStream_t s, bool temp, size_t bytes, v
 void mem_free(const fem_mem &m, hipStream_t s, bool temp, void *p);
 
 // ---- incidence and sparsity (fem_sparsity.hip) ----
+// Device address and size of the static scratch array on `device`, looked up
+// once per device (that device must be current at the first call).
+hipError_t static_scratch(int device, void **ptr, size_t *bytes);
 hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hipStream_t s);
 // Fills n int32 with value (a kernel, not a memset node).
 hipError_t fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);

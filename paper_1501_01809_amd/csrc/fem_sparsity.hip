@@ -10,6 +10,15 @@
 // only for counting and for bucketing, and every bucket is sorted afterwards.
 #include "fem_internal.h"
 
+#include <mutex>
+
+// Scratch of fem_build_sparsity_noalloc: a fixed array in every device's
+// global memory, held for the life of the process.  Host code never uses
+// the array's name as an address: static_scratch() looks its device address
+// up once per device.
+constexpr size_t FEM_STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[FEM_STATIC_SCRATCH_BYTES];
+
 namespace femk {
 namespace {
 
@@ -213,6 +222,25 @@ hipError_t check_range(const int32_t *v, int64_t n, int64_t limit, int *flag, hi
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_range, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n, limit, flag);
     return hipGetLastError();
+}
+
+hipError_t static_scratch(int device, void **ptr, size_t *bytes)
+{
+    static std::mutex mu;
+    static void *addr[64] = {};
+    *ptr = nullptr;
+    *bytes = 0;
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    *bytes = FEM_STATIC_SCRATCH_BYTES;
+    return hipSuccess;
 }
 
 int64_t scan_scratch(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }

@@ -87,7 +87,7 @@ RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_ctx_set_allocator", "fem_last_error",
            "fem_sync",
-           "fem_build_sparsity", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
+           "fem_build_sparsity", "fem_build_sparsity_noalloc", "fem_plan_create", "fem_plan_destroy", "fem_plan_info",
            "fem_par_loop_assemble_mat", "fem_par_loop_assemble_vec", "fem_apply_action",
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
@@ -116,6 +116,8 @@ def lib():
         L.fem_sync.argtypes = [P]
         L.fem_build_sparsity.argtypes = [P, C.POINTER(fem_map), C.POINTER(fem_map), C.POINTER(fem_sparsity), P,
                                          C.POINTER(C.c_size_t)]
+        L.fem_build_sparsity_noalloc.argtypes = [P, C.POINTER(fem_map), C.POINTER(fem_map),
+                                                 C.POINTER(fem_sparsity)]
         L.fem_plan_create.argtypes = [P, C.POINTER(fem_form), C.POINTER(fem_args), C.POINTER(fem_sparsity),
                                       C.POINTER(P)]
         L.fem_plan_destroy.argtypes = [P]; L.fem_plan_destroy.restype = None
@@ -355,6 +357,22 @@ def fem_build_sparsity(ctx: Context, rmap, nrows: int, cmap=None, ncols: int | N
     if buf is not None:
         buf.record_stream(ctx.stream)   # in use until the queued fill pass has run
     return Sparsity(row_ptr, col_idx[:sp.nnz], nrows, ncols)
+
+
+def fem_build_sparsity_noalloc(ctx: Context, rmap, nrows: int, row_ptr, col_idx=None):
+    """The allocation-free sparsity build on caller tensors: with col_idx None
+    the counting pass (fills row_ptr, returns nnz), else the fill pass into
+    col_idx (its first nnz entries).  Scratch comes from the library's static
+    array; the library allocates nothing."""
+    cells = fem_set(rmap.shape[0]); rs = fem_set(nrows)
+    rm = fem_map(C.pointer(cells), C.pointer(rs), rmap.shape[1], _ptr(rmap))
+    sp = fem_sparsity(0, 0, 0, _ptr(row_ptr), None)
+    if col_idx is not None:
+        sp.nrows, sp.ncols = nrows, nrows
+        sp.nnz = int(row_ptr[-1].item())
+        sp.col_idx = C.c_void_p(col_idx.data_ptr())
+    ctx.check(lib().fem_build_sparsity_noalloc(ctx.h, C.byref(rm), C.byref(rm), C.byref(sp)))
+    return sp.nnz
 
 
 def fem_expand_sparsity(ctx: Context, sp: Sparsity, bs: int) -> Sparsity:
