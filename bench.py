@@ -281,18 +281,22 @@ def bench_precision(ctx, steps: int, warmup: int, seed: int, n: int = 48):
     return out
 
 
-def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: int = 4,
-                  max_wait_ms: float = 100.0):
+def bench_serving(ctx, seed: int, nreq: int = 4096, loads=(0.5, 0.8, 1.2), slots: int = 4,
+                  max_wait_ms: float = 100.0, max_batch: int = 64):
     """The serving workload: a stream of `nreq` requests with Poisson arrivals
-    at rate load / s, s the mean isolated service time of the mix.  Each
-    request is an assembly (CSR matrix + right-hand side) or a matrix-free
-    action, drawn uniformly, on a resident model drawn uniformly by mesh kind
-    (unit-square triangles, n in 16..512; Kuhn cubes, n in 8..64), size and
-    Lagrange degree 1..3; jittered meshes, fields U[0.5, 1.5].  The same
-    arrival sequence is served with `slots` slots and with one slot (no
-    overlap), and with `slots` slots admitting the smallest queued request
-    first (a queue head that has waited max_wait_ms goes first).  Latency =
-    completion seen by the poll loop minus arrival."""
+    at rate load / s, s the mean isolated service time of the mix, for each
+    load in `loads`.  Each request is an assembly (CSR matrix + right-hand
+    side) or a matrix-free action, drawn uniformly, on a resident model drawn
+    uniformly by mesh kind (unit-square triangles, n in 16..512; Kuhn cubes,
+    n in 8..64), size and Lagrange degree 1..3; jittered meshes, fields
+    U[0.5, 1.5].  The same request sequence (arrival times scaled by the
+    load) is served by each policy: `slots` slots with batches of up to
+    `max_batch` requests in shared persistent launches, in arrival order
+    ("batched") or smallest first with a queue head that has waited
+    max_wait_ms going first ("batched_shortest"); and one slot with one
+    request per launch ("one_slot", requests served one at a time).  Latency =
+    completion seen by the poll loop minus arrival; cells/s = cells of the
+    requests / makespan."""
     import torch
     import fem_inputs as fi
     from paper_1501_01809_amd import fem as F
@@ -300,7 +304,7 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
     kinds = {"square": [16, 32, 64, 128, 256, 512], "cube": [8, 16, 32, 64]}
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     rng = np.random.default_rng(seed + 5)
-    specs, keep = [], []
+    specs = []
     t0 = time.perf_counter()
     for kind, sizes in kinds.items():
         for n in sizes:
@@ -340,6 +344,8 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
         srv_.release(rid)
         return td
 
+    srv.configure(1, False)
+    srv.set_batch(1)
     # service time of every (model, op) alone with warm caches (best of two
     # after a warm-up), for reference
     iso = {}
@@ -359,23 +365,20 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
     # so that caches hold what a stream of mixed requests leaves in them
     sample = [draw() for _ in range(512)]
     sbar = float(np.mean([serve_one(srv, sp_, op) for sp_, op in sample]))
-    rate = load / sbar
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    reqs = []
-    for i in range(nreq):
-        sp_, op = draw()
-        reqs.append((sp_, op, float(arrivals[i])))
+    gaps = rng.exponential(1.0, nreq)          # unit-rate gaps, scaled per load
+    mix = [draw() for _ in range(nreq)]
 
-    def run(srv_):
+    def run(srv_, arrivals):
         lat = np.zeros(nreq); svc = np.zeros(nreq); cells = 0
         ids = {}
         nxt = 0; done = 0
         c0 = time.perf_counter()
         while done < nreq:
             now = time.perf_counter() - c0
-            while nxt < nreq and reqs[nxt][2] <= now:
-                sp_, op, ta = reqs[nxt]
-                rid = srv_.submit(sp_["id"], op, sp_["g"]["x"] if op == F.FEM_REQ_ACTION else None, ta)
+            while nxt < nreq and arrivals[nxt] <= now:
+                sp_, op = mix[nxt]
+                rid = srv_.submit(sp_["id"], op, sp_["g"]["x"] if op == F.FEM_REQ_ACTION else None,
+                                  float(arrivals[nxt]))
                 ids[rid] = nxt
                 nxt += 1
             c, _, _ = srv_.poll(now)
@@ -383,35 +386,44 @@ def bench_serving(ctx, seed: int, nreq: int = 4096, load: float = 0.8, slots: in
                 for rid in srv_.take_completed():
                     _, _, ta, td = srv_.result(rid)
                     i = ids.pop(rid)
-                    lat[i] = td - reqs[i][2]
+                    lat[i] = td - arrivals[i]
                     svc[i] = td - ta
-                    cells += reqs[i][0]["cells"]
+                    cells += mix[i][0]["cells"]
                     srv_.release(rid)
                     done += 1
         span = time.perf_counter() - c0
         return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3), "makespan_s": span, "cells_per_s": cells / span,
-                "admit_to_done_mean_ms": float(svc.mean() * 1e3)}
+                "mean_ms": float(lat.mean() * 1e3), "makespan_s": span, "arrival_span_s": float(arrivals[-1]),
+                "cells_per_s": cells / span, "admit_to_done_mean_ms": float(svc.mean() * 1e3)}
 
-    out = {"workload": f"{nreq} requests, Poisson arrivals at {load} / mean isolated service time; assembly "
-                       f"(CSR + RHS) or action, unit-square triangle meshes n=16..512 and Kuhn cubes n=8..64, "
-                       f"P1-P3, fields U[0.5,1.5]; {len(specs)} resident models",
+    out = {"workload": f"{nreq} requests, Poisson arrivals at load x (1 / mean isolated service time) for load in "
+                       f"{list(loads)}; assembly (CSR + RHS) or action, unit-square triangle meshes n=16..512 and "
+                       f"Kuhn cubes n=8..64, P1-P3, fields U[0.5,1.5]; {len(specs)} resident models",
            "models": len(specs), "resident_bytes": resident, "inputs_ms": build_ms, "setup_ms": setup_ms,
-           "mean_isolated_service_ms": sbar * 1e3, "arrival_rate_per_s": rate, "slots": slots,
+           "mean_isolated_service_ms": sbar * 1e3, "slots": slots, "max_batch": max_batch,
+           "shortest_max_wait_ms": max_wait_ms,
            "isolated_ms": {f"{sp_['kind']}{sp_['n']}p{sp_['degree']}": [round(iso[(sp_['id'], 0)] * 1e3, 3),
                                                                        round(iso[(sp_['id'], 1)] * 1e3, 3)]
-                           for sp_ in specs}}
+                           for sp_ in specs}, "loads": {}}
     log(f"serving: {len(specs)} models resident ({resident / 1e9:.1f} GB), setup {setup_ms / 1e3:.1f} s, "
-        f"mean isolated service {sbar * 1e3:.3f} ms; {slots} slots")
-    out["shortest_max_wait_ms"] = max_wait_ms
-    for name, ns, share, order in (("batched", slots, True, F.FEM_SERVE_FIFO),
-                                   ("batched_shortest", slots, True, F.FEM_SERVE_SHORTEST),
-                                   ("batched_full_grid", slots, False, F.FEM_SERVE_FIFO),
-                                   ("one_slot", 1, False, F.FEM_SERVE_FIFO)):
-        srv.configure(ns, share)
-        srv.set_order(order, max_wait_ms * 1e-3)
-        out[name] = run(srv)
-        log(f"serving: {name} ({ns} slots) p50 {out[name]['p50_ms']:.2f} ms p99 {out[name]['p99_ms']:.2f} ms")
+        f"mean isolated service {sbar * 1e3:.3f} ms; {slots} slots, batches of up to {max_batch}")
+    # (name, slots, requests per batch, order, Mat launches on half the CUs
+    # while others run); one slot has nothing to share the GPU with
+    policies = (("batched", slots, max_batch, F.FEM_SERVE_FIFO, True),
+                ("batched_shortest", slots, max_batch, F.FEM_SERVE_SHORTEST, True),
+                ("batched_full_grid", slots, max_batch, F.FEM_SERVE_FIFO, False),
+                ("one_slot", 1, 1, F.FEM_SERVE_FIFO, False))
+    for load in loads:
+        arrivals = np.cumsum(gaps) * sbar / load
+        rec = {"arrival_rate_per_s": load / sbar}
+        for name, ns, nb, order, share in policies:
+            srv.configure(ns, share)
+            srv.set_batch(nb)
+            srv.set_order(order, max_wait_ms * 1e-3)
+            rec[name] = run(srv, arrivals)
+            log(f"serving: load {load} {name}: p50 {rec[name]['p50_ms']:.2f} ms p99 {rec[name]['p99_ms']:.2f} ms "
+                f"{rec[name]['cells_per_s']:.3g} cells/s")
+        out["loads"][str(load)] = rec
     srv.close()
     return out
 

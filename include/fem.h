@@ -473,21 +473,28 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
  * A request is FEM_REQ_ASSEMBLE (the CSR matrix and the right-hand side
  * integral of f v, WRITE) or FEM_REQ_ACTION (y = A x for the caller's x on the
  * model's nodes).  Submitted requests queue in arrival order.
- * fem_server_poll, which never blocks, retires requests whose work has
- * finished and admits the queue head (or, by fem_server_set_order, the
- * smallest queued request) while one of the `slots` is free and the
- * request's outputs fit the HBM budget (hbm_budget bytes for resident models
- * plus outputs in flight).  Outputs come from an arena of the budget left
+ * fem_server_poll, which never blocks, retires batches whose work has
+ * finished and, while one of the `slots` is free, admits a batch: queued
+ * requests taken in admission order (the queue head first, or by
+ * fem_server_set_order the smallest) up to fem_server_set_batch's limit (64
+ * by default) and as long as each request's outputs fit the HBM budget
+ * (hbm_budget bytes for resident models plus outputs in flight).  A batch's
+ * work is queued on its slot's stream as one persistent launch per kernel
+ * (Mat, source vector, action) and (dimension, degree) present, whose
+ * workgroups take (request, row blocks) work items from a device counter:
+ * requests of different meshes and degrees share launches, and batches
+ * admitted while others run overlap with them on the device.  A request
+ * completes with its batch.  Outputs come from an arena of the budget left
  * after the resident models, allocated at the first admission (so models
  * must be added before the first poll that admits a request) and carved on
- * the host without driver calls.  An admitted request's kernels are queued
- * on its slot's stream, so requests admitted while others run overlap with
- * them on the device.  Its outputs
+ * the host without driver calls.  Its outputs
  * (device pointers from fem_server_result: CSR values in the model's
  * sparsity order and the vector, or y) stay valid until fem_server_release
  * returns their memory to the budget.  Results do not depend on the mix:
- * each request's kernels read only its own inputs and sum in a fixed order,
- * so they are bitwise the same alone and with any other requests in flight.
+ * every row block is computed by the same code and in the same order as by
+ * the single-request kernels and reads only its own request's inputs, so a
+ * result is bitwise the same alone, batched with any other requests, and as
+ * fem_par_loop_assemble_mat / _vec and fem_apply_action compute it.
  * `now` and `arrival_time` are the caller's clock (seconds); the server
  * stamps admission and completion with the `now` of the poll that saw them.
  * The server owns its slot streams (default priority); it restores the
@@ -511,11 +518,14 @@ fem_status fem_server_release(fem_server *server, int64_t request_id);
  * handed out, in completion order; *n receives the count. */
 fem_status fem_server_take_completed(fem_server *server, int64_t *ids, int32_t cap, int32_t *n);
 /* Admission policy: use only the first `slots` slots (1..the number created;
- * requests already running elsewhere finish normally); with share_cus != 0
- * (the default) a CSR assembly admitted while other requests run or wait
- * launches its persistent Mat kernel on half the compute units, so that it
+ * batches already running elsewhere finish normally); with share_cus != 0
+ * (the default) a batch admitted while other batches run or requests wait
+ * launches its persistent Mat kernels on half the compute units, so that it
  * does not shut the others out for its whole duration. */
 fem_status fem_server_configure(fem_server *server, int32_t slots, int32_t share_cus);
+/* Requests per batch, 1..64 (1: every request runs in launches of its own).
+ * FEM_E_ARG outside that range. */
+fem_status fem_server_set_batch(fem_server *server, int32_t max_requests);
 /* Which queued request admission takes next.  FEM_SERVE_FIFO (the default):
  * the queue head.  FEM_SERVE_SHORTEST: the queued request of least estimated
  * work (cell visits of its plan times the local tensor size, plus the Mat

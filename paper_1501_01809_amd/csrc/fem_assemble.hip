@@ -41,6 +41,7 @@ struct KArgs {
     const int32_t *__restrict__ blk_cptr;
     const int32_t *__restrict__ bcell;
     const int32_t *__restrict__ bverts;
+    const int32_t *__restrict__ bnodes;
     const int32_t *__restrict__ inc_ptr;
     const uint16_t *__restrict__ ent;
     const int32_t *__restrict__ blk_hdr;
@@ -48,6 +49,7 @@ struct KArgs {
     const int32_t *__restrict__ wq;
     const uint32_t *__restrict__ pstream;   // batches of MAT_BATCH 16-bit indices
     const int64_t *__restrict__ row_ptr;
+    const int32_t *__restrict__ col_idx;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
     const double *__restrict__ coeff;
@@ -61,10 +63,10 @@ KArgs kargs(const AsmArgs &a)
 {
     const fem_plan &p = *a.plan;
     KArgs k;
-    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts;
+    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts; k.bnodes = p.bnodes;
     k.inc_ptr = p.inc_ptr; k.ent = p.ent;
     k.blk_hdr = p.blk_hdr; k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint32_t *>(p.pstream);
-    k.row_ptr = a.row_ptr; k.coords = a.coords;
+    k.row_ptr = a.row_ptr; k.col_idx = a.col_idx; k.coords = a.coords;
     k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
     return k;
@@ -459,7 +461,7 @@ __device__ __forceinline__ void chunk_stream(const KArgs &a, const MatBlk &h, in
 // register is consumed before a younger load is waited for, so the
 // compiler's waits stay exact and never drain the prefetches.
 template <int D, int K>
-__global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, int nblk)
+__device__ __forceinline__ void mat_blocks(const KArgs &a, int bb, int be)
 {
     using T = typename TabOf<D, K>::T;
     using L = MatLds<D, K>;
@@ -475,10 +477,6 @@ __global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, in
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int lcc = tid % CCH, part = tid / CCH;
     const bool has_item = tid < CCH * LPC;
-    const int G = gridDim.x, bid = blockIdx.x;
-    const int rank = G % 8 == 0 ? (bid % 8) * (G / 8) + bid / 8 : bid;
-    const int bb = (int)((int64_t)nblk * rank / G), be = (int)((int64_t)nblk * (rank + 1) / G);
-    if (bb >= be) return;
     double *__restrict__ E = lds + L::SCAP + lcc * NE;
 
     MatBlk h = mat_blk(a, bb);
@@ -570,10 +568,124 @@ __global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, in
     }
 }
 
+// Persistent: one workgroup per CU walks a contiguous range of the blocks
+// (XCD-grouped, above).
+template <int D, int K>
+__global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, int nblk)
+{
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int rank = G % 8 == 0 ? (bid % 8) * (G / 8) + bid / 8 : bid;
+    const int bb = (int)((int64_t)nblk * rank / G), be = (int)((int64_t)nblk * (rank + 1) / G);
+    if (bb >= be) return;
+    mat_blocks<D, K>(a, bb, be);
+}
+
+// ---------------------------------------------------------------- P1 Mat by row groups
+
+// P1 matrices have few values per row (7 on triangles, 15 on tetrahedra of a
+// Kuhn mesh) and many cells per value, so a per-contribution schedule costs
+// more bytes than the values.  Instead a group of G lanes owns one row at a
+// time, lane j the row's j-th column: the lanes walk the row's incident cells
+// (the Dat plan's entries, ascending cell id) and each adds the element entry
+// whose column node is its own, found by comparing its column with the
+// cell's vertex ids.  The sum of every value is held in a register, in
+// ascending cell order (the same order, hence the same bits, as the stream
+// kernel), and the row is written once, coalesced.  The block's element
+// matrices and vertex ids live in LDS; a workgroup of RG_WG lanes holds up to
+// RgLds<D>::CMAX cells.
+constexpr int RG_WG = 1024;
+
+template <int D> struct RgLds {
+    static constexpr int NV = D + 1, NE = NV * (NV + 1) / 2;
+    static constexpr int CMAX = (LDS_DOUBLES * 8) / (NE * 8 + NV * 4);
+};
+
+// Packed upper-triangle index of (li, lj) in an element matrix of NV nodes.
+template <int NV>
+__device__ __forceinline__ int upper_idx(int li, int lj)
+{
+    const int i = min(li, lj), j = max(li, lj);
+    return i * (2 * NV - i + 1) / 2 + (j - i);
+}
+
+template <int D, int G>
+__device__ __forceinline__ void mat_rg_block(const KArgs &a, int b)
+{
+    using L = RgLds<D>;
+    constexpr int NV = L::NV, NE = L::NE, CM = L::CMAX, NG = RG_WG / G;
+    static_assert(NE == TabOf<D, 1>::T::NE, "packed P1 element matrix");
+    __shared__ double e_lds[CM * NE];
+    __shared__ int32_t v_lds[CM * NV];
+    const int tid = threadIdx.x;
+    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
+    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
+    // 1. the block's cells: vertex ids and element matrices into LDS (the
+    //    next pass's gather is in flight while a pass computes)
+    // (the node ids the columns are compared with are the vertex ids when the
+    // plan found the two Maps equal, else the plan's per-visit node ids)
+    CellIn<D> cin;
+    int32_t vid[NV], nid[NV];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) vid[m] = a.bverts[(int64_t)(c0 + c) * NV + m];
+        issue_coords<D>(vid, a.coords, a.coeff, cin);
+        if (a.bnodes) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) nid[m] = a.bnodes[(int64_t)(c0 + c) * NV + m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) nid[m] = vid[m];
+        }
+    };
+    if (tid < nc) fetch(tid);
+    for (int cs = 0; cs < nc; cs += RG_WG) {
+        const int c = cs + tid;
+        if (c < nc) {
+            double E[NE];
+            cell_tensor<D, 1>(0, cin, a.cstiff, a.cmass, E);
+#pragma unroll
+            for (int q = 0; q < NE; ++q) e_lds[c * NE + q] = E[q];
+#pragma unroll
+            for (int m = 0; m < NV; ++m) v_lds[c * NV + m] = nid[m];
+        }
+        if (c + RG_WG < nc) fetch(c + RG_WG);
+    }
+    lds_barrier();
+    // 2. rows: group g takes rows r0 + g, r0 + g + NG, ...; lane j its j-th column
+    const int g = tid / G, j = tid % G;
+    for (int r = r0 + g; r < r1; r += NG) {
+        const int64_t p0 = a.row_ptr[r];
+        const int len = (int)(a.row_ptr[r + 1] - p0);
+        const int32_t col = j < len ? a.col_idx[p0 + j] : -1;
+        const int e0 = a.inc_ptr[r], e1 = a.inc_ptr[r + 1];
+        double acc = -0.0;
+        for (int eb = e0; eb < e1; eb += G) {
+            // G entries at once, one per lane, then broadcast in the group
+            const uint32_t mine = eb + j < e1 ? (uint32_t)a.ent[eb + j] : 0u;
+            const int ne = min(G, e1 - eb);
+            for (int k = 0; k < ne; ++k) {
+                const uint32_t w = (uint32_t)__shfl((int)mine, k, G);
+                const int lc = (int)(w >> 2), li = (int)(w & 3u);
+                int lj = -1;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) lj = v_lds[lc * NV + m] == col ? m : lj;
+                if (lj >= 0) acc += e_lds[lc * NE + upper_idx<NV>(li, lj)];
+            }
+        }
+        if (j < len) a.out[p0 + j] = a.inc ? a.out[p0 + j] + acc : acc;
+    }
+}
+
+template <int D, int G>
+__global__ __launch_bounds__(RG_WG) void k_mat_rg(KArgs a)
+{
+    mat_rg_block<D, G>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- Dat / action
 
 template <int D, int K, bool ACTION>
-__global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArgs a)
+__device__ __forceinline__ void vec_block(const KArgs &a, int b)
 {
     constexpr int WG = VecWG<D, K, ACTION>::WG, KR = VecWG<D, K, ACTION>::KR;
     using T = typename TabOf<D, K>::T;
@@ -581,7 +693,7 @@ __global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArg
     constexpr int NP = (D + 1) * Geo<D>::NM;
     constexpr int CAP = VLDS / NL;
     __shared__ double vk[CAP * NL];
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
     constexpr bool PRE = !ACTION || ActCfg<D, K>::PREFETCH;
     const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
@@ -657,9 +769,32 @@ __global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArg
     }
 }
 
+// One workgroup per row block.
+template <int D, int K, bool ACTION>
+__global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArgs a)
+{
+    vec_block<D, K, ACTION>(a, blockIdx.x);
+}
+
+template <int D>
+hipError_t rg_dispatch(const AsmArgs &a, hipStream_t s)
+{
+    const dim3 grid(a.plan->nblk), block(RG_WG);
+    switch (a.plan->rg) {
+    case 8: hipLaunchKernelGGL((k_mat_rg<D, 8>), grid, block, 0, s, kargs(a)); break;
+    case 16: hipLaunchKernelGGL((k_mat_rg<D, 16>), grid, block, 0, s, kargs(a)); break;
+    case 32: hipLaunchKernelGGL((k_mat_rg<D, 32>), grid, block, 0, s, kargs(a)); break;
+    case 64: hipLaunchKernelGGL((k_mat_rg<D, 64>), grid, block, 0, s, kargs(a)); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int D, int K>
 hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
+    if constexpr (K == 1)
+        if (a.plan->rg) return rg_dispatch<D>(a, s);
     const int nblk = a.plan->nblk;
     const int grid = std::min(nblk, std::max(a.num_cus, 1));
     hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(grid), dim3(MatCfg<D, K>::WG), 0, s, kargs(a), nblk);
@@ -667,6 +802,8 @@ hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 }
 
 }  // namespace
+
+int rg_cell_cap(int dim) { return dim == 2 ? RgLds<2>::CMAX : RgLds<3>::CMAX; }
 
 bool limits(int dim, int degree, bool is_mat, Limits *out)
 {
@@ -719,7 +856,178 @@ hipError_t action_dispatch(const AsmArgs &a, hipStream_t s)
     hipLaunchKernelGGL((k_assemble_vec<D, K, true>), dim3(a.plan->nblk), dim3(VecWG<D, K, true>::WG), 0, s, kargs(a));
     return hipGetLastError();
 }
+// ---------------------------------------------------------------- batched launches
+
+// One launch over the work of several requests whose plans share (dim,
+// degree): the descriptor holds a work-item counter, the requests' first
+// work items (prefix sums) and block counts, then their arguments.  Every
+// workgroup takes the next work item from the counter until none is left (so
+// every wave leaves the loop), finds its request and runs that request's
+// blocks with the same code as the single-request kernels: a block's
+// values do not depend on what else is in the launch.
+struct BatchHdr {
+    int32_t counter, nreq, bpi, total;
+};
+
+__device__ __forceinline__ int batch_item(BatchHdr *hdr, int &it)
+{
+    __shared__ int s_it;
+    __syncthreads();                       // the previous item's LDS reads are done
+    if (threadIdx.x == 0) s_it = atomicAdd(&hdr->counter, 1);
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_it);
+    return it < ldc(&hdr->total);
+}
+
+// A request's arguments through scalar loads (the index is uniform).
+__device__ __forceinline__ KArgs load_kargs(const KArgs *p)
+{
+    static_assert(sizeof(KArgs) % 8 == 0, "KArgs in 8-byte words");
+    KArgs k;
+    uint64_t *d = reinterpret_cast<uint64_t *>(&k);
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(KArgs) / 8); ++i) d[i] = ldc(src + i);
+    return k;
+}
+
+__device__ __forceinline__ int batch_request(const int32_t *prefix, int it)
+{
+    int r = 0;
+    while (ldc(prefix + r + 1) <= it) ++r;
+    return r;
+}
+
+template <int D, int K>
+__global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_mat_batch(BatchHdr *hdr, const int32_t *prefix,
+                                                                   const int32_t *nblk, const KArgs *reqs)
+{
+    const int bpi = ldc(&hdr->bpi);
+    int it;
+    while (batch_item(hdr, it)) {
+        const int r = batch_request(prefix, it);
+        const KArgs a = load_kargs(reqs + r);
+        const int bb = (it - ldc(prefix + r)) * bpi;
+        const int be = min(bb + bpi, ldc(nblk + r));
+        mat_blocks<D, K>(a, bb, be);
+    }
+}
+
+template <int D, int K, bool ACTION>
+__global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_vec_batch(BatchHdr *hdr, const int32_t *prefix,
+                                                                          const KArgs *reqs)
+{
+    int it;
+    while (batch_item(hdr, it)) {
+        const int r = batch_request(prefix, it);
+        const KArgs a = load_kargs(reqs + r);
+        vec_block<D, K, ACTION>(a, it - ldc(prefix + r));
+    }
+}
+
+template <int D, int G>
+__global__ __launch_bounds__(RG_WG) void k_mat_rg_batch(BatchHdr *hdr, const int32_t *prefix, const KArgs *reqs)
+{
+    int it;
+    while (batch_item(hdr, it)) {
+        const int r = batch_request(prefix, it);
+        const KArgs a = load_kargs(reqs + r);
+        mat_rg_block<D, G>(a, it - ldc(prefix + r));
+    }
+}
+
+constexpr int BATCH_BPI = 8;   // Mat blocks per work item (pipelined within the item)
+
+struct BatchLayout {
+    size_t prefix, nblk, reqs, bytes;
+    explicit BatchLayout(int nreq)
+    {
+        prefix = 256;
+        nblk = prefix + ((size_t)(nreq + 1) * 4 + 15) / 16 * 16;
+        reqs = nblk + ((size_t)nreq * 4 + 15) / 16 * 16;
+        bytes = (reqs + (size_t)nreq * sizeof(KArgs) + 255) / 256 * 256;
+    }
+};
+
+template <int D, int K>
+hipError_t batch_dispatch(int op, int rg, int grid, char *desc, const BatchLayout &L, int total, hipStream_t s)
+{
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(desc);
+    const int32_t *prefix = reinterpret_cast<const int32_t *>(desc + L.prefix);
+    const int32_t *nblk = reinterpret_cast<const int32_t *>(desc + L.nblk);
+    const KArgs *reqs = reinterpret_cast<const KArgs *>(desc + L.reqs);
+    if (op == 0 && rg) {
+        if constexpr (K == 1) {
+            const dim3 g(std::min(grid, total)), b(RG_WG);
+            switch (rg) {
+            case 8: hipLaunchKernelGGL((k_mat_rg_batch<D, 8>), g, b, 0, s, hdr, prefix, reqs); break;
+            case 16: hipLaunchKernelGGL((k_mat_rg_batch<D, 16>), g, b, 0, s, hdr, prefix, reqs); break;
+            case 32: hipLaunchKernelGGL((k_mat_rg_batch<D, 32>), g, b, 0, s, hdr, prefix, reqs); break;
+            case 64: hipLaunchKernelGGL((k_mat_rg_batch<D, 64>), g, b, 0, s, hdr, prefix, reqs); break;
+            default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    if (op == 0) {
+        hipLaunchKernelGGL((k_mat_batch<D, K>), dim3(std::min(grid, total)), dim3(MatCfg<D, K>::WG), 0, s, hdr,
+                           prefix, nblk, reqs);
+    } else if (op == 1) {
+        hipLaunchKernelGGL((k_vec_batch<D, K, false>), dim3(std::min(2 * grid, total)),
+                           dim3(VecWG<D, K, false>::WG), 0, s, hdr, prefix, reqs);
+    } else {
+        hipLaunchKernelGGL((k_vec_batch<D, K, true>), dim3(std::min(2 * grid, total)),
+                           dim3(VecWG<D, K, true>::WG), 0, s, hdr, prefix, reqs);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t batch_desc_bytes(int nreq) { return BatchLayout(nreq).bytes; }
+
+hipError_t launch_batch(int op, const AsmArgs *reqs, int nreq, int grid, void *hdesc, void *desc, hipStream_t s)
+{
+    if (nreq <= 0) return hipSuccess;
+    const fem_plan &p0 = *reqs[0].plan;
+    for (int r = 0; r < nreq; ++r)
+        if (reqs[r].plan->dim != p0.dim || reqs[r].plan->degree != p0.degree || reqs[r].plan->is_mat != (op == 0) ||
+            reqs[r].plan->rg != p0.rg)
+            return hipErrorInvalidValue;
+    const BatchLayout L(nreq);
+    char *h = static_cast<char *>(hdesc);
+    std::fill(h, h + L.bytes, 0);
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(h);
+    int32_t *prefix = reinterpret_cast<int32_t *>(h + L.prefix);
+    int32_t *nblk = reinterpret_cast<int32_t *>(h + L.nblk);
+    KArgs *ka = reinterpret_cast<KArgs *>(h + L.reqs);
+    const int bpi = op == 0 && !p0.rg ? BATCH_BPI : 1;   // one block per item for the one-block kernels
+    prefix[0] = 0;
+    for (int r = 0; r < nreq; ++r) {
+        nblk[r] = reqs[r].plan->nblk;
+        prefix[r + 1] = prefix[r] + (nblk[r] + bpi - 1) / bpi;
+        ka[r] = kargs(reqs[r]);
+    }
+    hdr->counter = 0;
+    hdr->nreq = nreq;
+    hdr->bpi = bpi;
+    hdr->total = prefix[nreq];
+    if (hdr->total == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(desc, hdesc, L.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const int total = hdr->total;
+    char *d = static_cast<char *>(desc);
+    switch (p0.dim * 10 + p0.degree) {
+    case 21: return batch_dispatch<2, 1>(op, p0.rg, grid, d, L, total, s);
+    case 22: return batch_dispatch<2, 2>(op, p0.rg, grid, d, L, total, s);
+    case 23: return batch_dispatch<2, 3>(op, p0.rg, grid, d, L, total, s);
+    case 31: return batch_dispatch<3, 1>(op, p0.rg, grid, d, L, total, s);
+    case 32: return batch_dispatch<3, 2>(op, p0.rg, grid, d, L, total, s);
+    case 33: return batch_dispatch<3, 3>(op, p0.rg, grid, d, L, total, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_mat(const AsmArgs &a, hipStream_t s)
 {

@@ -8,15 +8,19 @@
 // overheads are what batching amortises, "Experiments").
 //
 // Requests (an assembly: CSR matrix + right-hand side; or an action y = A x)
-// queue in arrival order.  fem_server_poll admits the queue head (or, when
-// asked, the queued request of least estimated work, with a bound on how
-// long the head can be passed over) whenever a slot is free and its output
-// memory fits the budget; an admitted request's
-// kernels go onto its slot's stream, so requests that arrive while others
-// are running start at once and overlap on the device with them.  The poll
-// also retires requests whose completion event has fired.  Every kernel is
-// deterministic and reads only its own request's data, so a result is
-// bitwise the same alone and in any mix.
+// queue in arrival order.  Whenever a slot is free, fem_server_poll takes a
+// batch of queued requests (the queue head first, or, when asked, the
+// requests of least estimated work, with a bound on how long the head can be
+// passed over) as long as their outputs fit the budget, and queues the
+// batch's work on the slot's stream as one persistent launch per kernel
+// (Mat, source vector, action) and (dimension, degree): the workgroups of a
+// launch take (request, row blocks) work items from a device counter, so
+// small requests share one launch and large ones spread over the whole GPU.
+// Batches admitted while others run overlap with them on the device.  The
+// poll also retires batches whose completion event has fired.  Every block
+// is computed by the same code, in the same order, as by the single-request
+// kernels, and reads only its own request's data, so a result is bitwise the
+// same alone and in any mix.
 #include <cstdarg>
 #include <cstdio>
 #include <deque>
@@ -122,17 +126,25 @@ struct Arena {
 
 }  // namespace
 
+// Requests of one batch (at most FEM_SERVE_MAX_BATCH), and the descriptor
+// memory of its launches: one (op, dimension, degree) group per launch.
+constexpr int FEM_SERVE_MAX_BATCH = 64;
+constexpr int FEM_SERVE_GROUPS = 26;     // 3 kernels x 6 (dimension, degree), P1 Mats by 4 row-group widths
+
 struct fem_server {
     fem_ctx *ctx = nullptr;
     hipStream_t home = nullptr;          // the context's stream at creation
     int64_t budget = 0, in_use = 0, resident = 0;
     int active = 0;                       // slots admission may use (<= streams.size())
-    int share_cus = 1;                    // halve the Mat kernel's grid while others run
+    int share_cus = 1;                    // halve the Mat launch's grid while others run
+    int max_batch = FEM_SERVE_MAX_BATCH;  // requests per batch
     int order = FEM_SERVE_FIFO;           // which queued request admission takes next
     double max_wait = 0;                  // FEM_SERVE_SHORTEST: a head waiting this long goes first
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
-    std::vector<int64_t> slot_req;        // request running on each slot, -1 if free
+    std::vector<std::vector<int64_t>> slot_reqs;   // the batch running on each slot (empty if free)
+    std::vector<void *> ddesc, hdesc;    // per slot: launch descriptors (device, pinned host staging)
+    size_t desc_bytes = 0;
     std::vector<Model *> models;
     std::vector<Request> reqs;
     std::deque<int64_t> queue;
@@ -169,18 +181,24 @@ fem_status fem_server_create(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fe
     s->home = ctx->stream;
     s->budget = hbm_budget;
     s->active = slots;
+    s->desc_bytes = FEM_SERVE_GROUPS * femk::batch_desc_bytes(FEM_SERVE_MAX_BATCH);
     for (int i = 0; i < slots; ++i) {
         hipStream_t st = nullptr;
         hipEvent_t ev = nullptr;
+        void *dd = nullptr, *hd = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = femk::mem_alloc(ctx->mem, ctx->stream, false, s->desc_bytes, &dd);
+        if (e == hipSuccess) e = hipHostMalloc(&hd, s->desc_bytes, hipHostMallocDefault);
+        if (st) s->streams.push_back(st);
+        if (ev) s->events.push_back(ev);
+        if (dd) s->ddesc.push_back(dd);
+        if (hd) s->hdesc.push_back(hd);
         if (e != hipSuccess) {
             fem_server_destroy(s);
-            return shed(ctx, e, "server_create: stream");
+            return shed(ctx, e, "server_create: slot");
         }
-        s->streams.push_back(st);
-        s->events.push_back(ev);
-        s->slot_req.push_back(-1);
+        s->slot_reqs.emplace_back();
     }
     *out = s;
     return FEM_OK;
@@ -198,6 +216,8 @@ void fem_server_destroy(fem_server *s)
         femk::mem_free(s->ctx->mem, nullptr, false, m->sp.col_idx);
         delete m;
     }
+    for (void *d : s->ddesc) femk::mem_free(s->ctx->mem, nullptr, false, d);
+    for (void *h : s->hdesc) (void)hipHostFree(h);
     for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->ctx) s->ctx->stream = s->home;
@@ -288,24 +308,75 @@ fem_status fem_server_submit(fem_server *s, int32_t model, int32_t op, const dou
     return FEM_OK;
 }
 
+// Queues one batch's work on a slot: per (kernel, dimension, degree), one
+// launch over every request of the batch that needs it.
+static fem_status launch_batch_on(fem_server *s, int slot, const std::vector<int64_t> &batch, bool busy)
+{
+    fem_ctx *ctx = s->ctx;
+    hipStream_t st = s->streams[slot];
+    // group: kernel (op), dimension and degree, and for P1 Mats the row-group width
+    std::map<int, std::vector<femk::AsmArgs>> groups;
+    for (int64_t rid : batch) {
+        const Request &r = s->reqs[rid];
+        const Model &m = *s->models[r.model];
+        femk::AsmArgs a{};
+        a.cell_vertex = m.cv.values;
+        a.coords = m.X.data;
+        a.cell_node = m.cn.values;
+        a.cstiff = 1.0;   // the Helmholtz form
+        a.cmass = 1.0;
+        a.num_cus = ctx->num_cus;
+        const int dk = ((int)m.form.cell - 2) * 3 + (m.form.degree - 1);
+        if (r.op == FEM_REQ_ASSEMBLE) {
+            femk::AsmArgs am = a;
+            am.plan = m.mplan; am.coeff = m.kappa.data; am.row_ptr = m.sp.row_ptr; am.col_idx = m.sp.col_idx;
+            am.out = r.values;
+            groups[(0 * 6 + dk) * 128 + m.mplan->rg].push_back(am);
+            femk::AsmArgs av = a;
+            av.plan = m.vplan; av.coeff = m.f.data; av.out = r.vec;
+            groups[(1 * 6 + dk) * 128].push_back(av);
+        } else {
+            femk::AsmArgs aa = a;
+            aa.plan = m.vplan; aa.coeff = m.kappa.data; aa.x = r.x; aa.out = r.vec;
+            groups[(2 * 6 + dk) * 128].push_back(aa);
+        }
+    }
+    // the Mat launch fills every CU while its work lasts; while other batches
+    // run or requests wait it takes half of them
+    const int cus = ctx->num_cus;
+    const int mat_grid = busy && s->share_cus ? (cus > 1 ? cus / 2 : 1) : cus;
+    size_t off = 0;
+    for (auto &kv : groups) {
+        const int op = kv.first / 128 / 6;
+        const std::vector<femk::AsmArgs> &gr = kv.second;
+        char *h = static_cast<char *>(s->hdesc[slot]) + off, *d = static_cast<char *>(s->ddesc[slot]) + off;
+        SHIP(femk::launch_batch(op, gr.data(), (int)gr.size(), op == 0 ? mat_grid : cus, h, d, st),
+             "poll: batched launch");
+        off += femk::batch_desc_bytes((int)gr.size());
+    }
+    SHIP(hipEventRecord(s->events[slot], st), "poll: event");
+    return FEM_OK;
+}
+
 fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_t *running, int32_t *queued)
 {
     if (!s) return FEM_E_ARG;
     fem_ctx *ctx = s->ctx;
     int32_t done = 0;
-    // retire
+    // retire finished batches
     for (size_t k = 0; k < s->streams.size(); ++k) {
-        const int64_t q = s->slot_req[k];
-        if (q < 0) continue;
+        if (s->slot_reqs[k].empty()) continue;
         const hipError_t e = hipEventQuery(s->events[k]);
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) return shed(ctx, e, "poll: request failed on the device");
-        Request &r = s->reqs[q];
-        r.state = 2;
-        r.t_done = now;
-        s->slot_req[k] = -1;
-        s->finished.push_back(q);
-        ++done;
+        for (int64_t q : s->slot_reqs[k]) {
+            Request &r = s->reqs[q];
+            r.state = 2;
+            r.t_done = now;
+            s->finished.push_back(q);
+            ++done;
+        }
+        s->slot_reqs[k].clear();
     }
     // the output arena: everything the resident models leave of the budget
     if (!s->arena.base && !s->queue.empty()) {
@@ -314,65 +385,52 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
         s->arena.size = size;
         s->arena.free_[0] = size;
     }
-    // admit while a slot is free and the next request's outputs fit: the
-    // queue head (FIFO), or the queued request of least estimated work
-    // (ties: the earlier) unless the head has waited max_wait or longer
+    // admit batches while a slot is free: the next request is the queue head
+    // (FIFO), or the queued request of least estimated work (ties: the
+    // earlier) unless the head has waited max_wait or longer; a batch closes
+    // at max_batch requests or at the first request whose outputs do not fit
     while (!s->queue.empty()) {
-        auto pick = s->queue.begin();
-        if (s->order == FEM_SERVE_SHORTEST && now - s->reqs[*pick].t_arrival < s->max_wait)
-            for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
-                if (s->reqs[*it].work < s->reqs[*pick].work) pick = it;
-        const int64_t rid = *pick;
-        Request &r = s->reqs[rid];
         int slot = -1;
         for (int k = 0; k < s->active; ++k)
-            if (s->slot_req[k] < 0) { slot = k; break; }
-        if (slot < 0 || s->resident + s->in_use + r.bytes > s->budget) break;
-        const Model &m = *s->models[r.model];
-        hipStream_t st = s->streams[slot];
-        // outputs from the arena (fragmentation may refuse what the budget
-        // allows: then wait for releases)
-        int64_t ov = -1, ob = -1;
-        if (!s->arena.take(8 * m.nrows, &ob)) break;
-        if (r.op == FEM_REQ_ASSEMBLE && !s->arena.take(8 * m.nnz, &ov)) {
-            s->arena.give(ob, 8 * m.nrows);
-            break;
+            if (s->slot_reqs[k].empty()) { slot = k; break; }
+        if (slot < 0) break;
+        std::vector<int64_t> batch;
+        while (!s->queue.empty() && (int)batch.size() < s->max_batch) {
+            auto pick = s->queue.begin();
+            if (s->order == FEM_SERVE_SHORTEST && now - s->reqs[*pick].t_arrival < s->max_wait)
+                for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+                    if (s->reqs[*it].work < s->reqs[*pick].work) pick = it;
+            const int64_t rid = *pick;
+            Request &r = s->reqs[rid];
+            if (s->resident + s->in_use + r.bytes > s->budget) break;
+            const Model &m = *s->models[r.model];
+            // outputs from the arena (fragmentation may refuse what the
+            // budget allows: then wait for releases)
+            int64_t ov = -1, ob = -1;
+            if (!s->arena.take(8 * m.nrows, &ob)) break;
+            if (r.op == FEM_REQ_ASSEMBLE && !s->arena.take(8 * m.nnz, &ov)) {
+                s->arena.give(ob, 8 * m.nrows);
+                break;
+            }
+            r.off_vec = ob; r.off_values = ov;
+            r.vec = reinterpret_cast<double *>(s->arena.base + ob);
+            r.values = ov >= 0 ? reinterpret_cast<double *>(s->arena.base + ov) : nullptr;
+            r.state = 1;
+            r.slot = slot;
+            r.t_admit = now;
+            s->in_use += r.bytes;
+            s->queue.erase(pick);
+            batch.push_back(rid);
         }
-        r.off_vec = ob; r.off_values = ov;
-        r.vec = reinterpret_cast<double *>(s->arena.base + ob);
-        r.values = ov >= 0 ? reinterpret_cast<double *>(s->arena.base + ov) : nullptr;
-        ctx->stream = st;
-        fem_status fs;
-        if (r.op == FEM_REQ_ASSEMBLE) {
-            fem_mat A{&m.sp, r.values};
-            fem_dat b{&m.nodes, 1, r.vec};
-            // the Mat kernel is persistent (one workgroup per CU); while other
-            // requests run or wait it takes half the CUs so that they are not
-            // shut out for its whole duration
-            bool busy = s->queue.size() > 1;
-            for (int64_t q : s->slot_req) busy |= q >= 0;
-            const int cus = ctx->num_cus;
-            if (busy && s->share_cus) ctx->num_cus = cus > 1 ? cus / 2 : 1;
-            fs = fem_par_loop_assemble_mat(ctx, m.mplan, &m.form, &m.args, &A, FEM_WRITE);
-            ctx->num_cus = cus;
-            if (fs == FEM_OK) fs = fem_par_loop_assemble_vec(ctx, m.vplan, &m.src, &m.args_f, &b, FEM_WRITE);
-        } else {
-            fem_dat xd{&m.nodes, 1, const_cast<double *>(r.x)};
-            fem_dat yd{&m.nodes, 1, r.vec};
-            fs = fem_apply_action(ctx, m.vplan, &m.form, &m.args, &xd, &yd, FEM_WRITE);
-        }
-        ctx->stream = s->home;
+        if (batch.empty()) break;
+        bool busy = !s->queue.empty();
+        for (const auto &b : s->slot_reqs) busy |= !b.empty();
+        fem_status fs = launch_batch_on(s, slot, batch, busy);
+        s->slot_reqs[slot] = batch;
         if (fs != FEM_OK) return fs;
-        SHIP(hipEventRecord(s->events[slot], st), "poll: event");
-        r.state = 1;
-        r.slot = slot;
-        r.t_admit = now;
-        s->in_use += r.bytes;
-        s->slot_req[slot] = rid;
-        s->queue.erase(pick);
     }
     int32_t run = 0;
-    for (int64_t q : s->slot_req) run += q >= 0;
+    for (const auto &b : s->slot_reqs) run += (int32_t)b.size();
     if (completed) *completed = done;
     if (running) *running = run;
     if (queued) *queued = (int32_t)s->queue.size();
@@ -429,6 +487,15 @@ fem_status fem_server_configure(fem_server *s, int32_t slots, int32_t share_cus)
         return sfail(s->ctx, FEM_E_ARG, "configure: slots must be 1..%d", (int)s->streams.size());
     s->active = slots;   // running requests on higher slots finish normally
     s->share_cus = share_cus != 0;
+    return FEM_OK;
+}
+
+fem_status fem_server_set_batch(fem_server *s, int32_t max_requests)
+{
+    if (!s) return FEM_E_ARG;
+    if (max_requests < 1 || max_requests > FEM_SERVE_MAX_BATCH)
+        return sfail(s->ctx, FEM_E_ARG, "set_batch: 1..%d requests per batch", FEM_SERVE_MAX_BATCH);
+    s->max_batch = max_requests;
     return FEM_OK;
 }
 

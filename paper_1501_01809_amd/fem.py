@@ -92,7 +92,7 @@ EXPORTS = ["fem_ctx_create", "fem_ctx_destroy", "fem_ctx_set_stream", "fem_ctx_s
            "fem_par_loop_assemble_adjoint", "fem_renumber", "fem_expand_sparsity",
            "fem_server_create", "fem_server_destroy", "fem_server_add_model", "fem_server_submit",
            "fem_server_poll", "fem_server_result", "fem_server_release", "fem_server_model_info",
-           "fem_server_configure", "fem_server_set_order", "fem_server_take_completed", "fem_par_loop_reduce",
+           "fem_server_configure", "fem_server_set_batch", "fem_server_set_order", "fem_server_take_completed", "fem_par_loop_reduce",
            "fem_apply_dirichlet", "fem_par_loop_assemble_mixed", "fem_facet_plan_create",
            "fem_par_loop_assemble_facets"]
 FEM_REQ_ASSEMBLE, FEM_REQ_ACTION = 0, 1
@@ -153,6 +153,7 @@ def lib():
         L.fem_server_release.argtypes = [P, C.c_int64]
         L.fem_server_configure.argtypes = [P, C.c_int32, C.c_int32]
         L.fem_server_set_order.argtypes = [P, C.c_int32, C.c_double]
+        L.fem_server_set_batch.argtypes = [P, C.c_int32]
         L.fem_server_take_completed.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
@@ -553,6 +554,10 @@ class Server:
 
     def configure(self, slots: int, share_cus: bool = True):
         self.ctx.check(lib().fem_server_configure(self.h, slots, int(share_cus)))
+
+    def set_batch(self, max_requests: int):
+        """Requests per batch (1: each request in launches of its own)."""
+        self.ctx.check(lib().fem_server_set_batch(self.h, max_requests))
 
     def set_order(self, order: int, max_wait: float = 0.0):
         """FEM_SERVE_FIFO or FEM_SERVE_SHORTEST (least estimated work first; a

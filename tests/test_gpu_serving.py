@@ -1,6 +1,7 @@
 """Request server: resident models, admission by slots and HBM budget,
-overlapping requests; every result bitwise the same alone and in a mix, and
-equal to the oracle on small meshes."""
+requests batched into shared persistent launches, overlapping batches; every
+result bitwise the same alone, in a batch, and as the single-request entry
+points compute it, and equal to the oracle on small meshes."""
 import time
 
 import numpy as np
@@ -80,33 +81,67 @@ def _workload(F, models, reps=3):
     return seq
 
 
+def _direct(F, p):
+    """The model's assembly and action through the single-request entry points."""
+    import torch
+    g = p["g"]
+    ctx = F.Context(0)
+    args = F.Args(g["cv"], g["X"], g["cn"], p["N"], [g["kappa"]])
+    args_f = F.Args(g["cv"], g["X"], g["cn"], p["N"], [g["f"]])
+    frm = F.form("helmholtz", p["dim"], p["degree"])
+    sp = F.fem_build_sparsity(ctx, g["cn"], p["N"])
+    mplan, vplan = F.fem_plan_create(ctx, frm, args, sp), F.fem_plan_create(ctx, frm, args, None)
+    vals = torch.empty(max(sp.col_idx.numel(), 1), dtype=torch.float64, device="cuda")
+    b = torch.empty(p["N"], dtype=torch.float64, device="cuda")
+    y = torch.empty_like(b)
+    F.fem_par_loop_assemble_mat(ctx, mplan, frm, args, vals, sp)
+    F.fem_par_loop_assemble_vec(ctx, vplan, F.form("source", p["dim"], p["degree"]), args_f, b)
+    F.fem_apply_action(ctx, vplan, frm, args, g["x"], y)
+    F.fem_sync(ctx)
+    return vals[:sp.col_idx.numel()].cpu().numpy(), b.cpu().numpy(), y.cpu().numpy()
+
+
 def test_alone_equals_mix_and_oracle():
     F, ctx, srv1, models = _server(1, 8 << 30)
+    srv1.set_batch(1)                                     # every request in launches of its own
     seq = _workload(F, models)
     alone = []
     for p, op in seq:                                     # one at a time, one slot
         rid = srv1.submit(p["id"], op, p["g"]["x"] if op == F.FEM_REQ_ACTION else None)
         res = _drain(srv1, F, [rid], {rid: p}, {rid: op})
         alone.append(res[rid])
-    # the same requests, all submitted at once to an 8-slot server
+    # the same requests, all submitted at once to a server with 8 slots and
+    # batches of up to 8 requests: mixed meshes, degrees and operations share
+    # launches, and batches overlap
     F2, ctx2, srv8, models8 = _server(8, 8 << 30)
+    srv8.set_batch(8)
     rids, mm, oo = [], {}, {}
     for p, op in seq:
         q = models8[p["id"]]
         r = srv8.submit(q["id"], op, q["g"]["x"] if op == F.FEM_REQ_ACTION else None)
         rids.append(r); mm[r] = q; oo[r] = op
+    _, running, queued = srv8.poll(0.0)
+    assert running == len(seq) and queued == 0, "one poll admits every request in batches"
     mix = _drain(srv8, F2, rids, mm, oo)
     for (p, op), a, r in zip(seq, alone, rids):
         b = mix[r]
         assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
         if op == F.FEM_REQ_ASSEMBLE:
             assert np.array_equal(a[0].view(np.uint64), b[0].view(np.uint64))
+    # and as the single-request entry points compute them
+    for k, p in enumerate(models):
+        vals, b, y = _direct(F, p)
+        i = 2 * k                                         # the first repetition: assembly, then action
+        assert seq[i][0] is p and seq[i][1] == F.FEM_REQ_ASSEMBLE
+        assert np.array_equal(alone[i][0].view(np.uint64), vals.view(np.uint64))
+        assert np.array_equal(alone[i][1].view(np.uint64), b.view(np.uint64))
+        assert np.array_equal(alone[i + 1][1].view(np.uint64), y.view(np.uint64))
     # every result against the oracle (first repetition)
     for (p, op), a in zip(seq[:2 * len(models)], alone):
         if op == F.FEM_REQ_ASSEMBLE:
             rp, ci = oracle.sparsity(p["cn"], p["N"])
             ref, absv = oracle.assemble_mat(p["dim"], p["degree"], p["cells"], p["coords"], p["cn"], p["kappa"], rp, ci)
-            check_close(a[0], ref, absv, f"server mat {p['dim']}D P{p['degree']}")
+            check_close(a[0], ref, absv, f"server mat {p['dim']}D P{p['degree']}", row_ptr=rp)
             b, ab = oracle.assemble_vec(p["dim"], p["degree"], p["cells"], p["coords"], p["cn"], p["f"], p["N"])
             check_close(a[1], b, ab, "server rhs")
         else:
@@ -157,6 +192,10 @@ def test_admission_respects_the_budget_and_slots():
 def test_server_rejections():
     F, ctx, srv, models = _server(2, 4 << 30, SPECS[:1])
     p = models[0]
+    for bad in (0, 65):
+        with pytest.raises(F.FemError) as e:
+            srv.set_batch(bad)
+        assert e.value.status == F.FEM_E_ARG
     with pytest.raises(F.FemError) as e:
         srv.submit(5, F.FEM_REQ_ASSEMBLE)
     assert e.value.status == F.FEM_E_ARG
@@ -178,6 +217,7 @@ def test_shortest_first_order():
     """FEM_SERVE_SHORTEST admits the smallest queued request first (unless the
     head has waited max_wait); results are bitwise those of FIFO admission."""
     F, ctx, srv, models = _server(1, 8 << 30)
+    srv.set_batch(1)                       # admission order is visible one request at a time
     big, small = models[5], models[0]      # a P3 tetrahedron assembly, a P1 triangle action
     with pytest.raises(F.FemError):
         srv.set_order(7, 0.0)
