@@ -54,16 +54,33 @@ def make_case(kind: str, n: int, degree: int, seed: int = 1501, jitter: float = 
                 np.ascontiguousarray(cn, dtype=np.int32), N, kappa, f, x)
 
 
-def check_close(got, ref, absref, what="", cabs=None):
+EPS = 2.0 ** -52
+
+
+def row_floor(absref, row_ptr):
+    """64 eps times the largest term scale of each entry's row (CSR order)."""
+    absref = np.asarray(absref); row_ptr = np.asarray(row_ptr)
+    lens = np.diff(row_ptr)
+    starts = row_ptr[:-1][lens > 0]
+    mx = np.maximum.reduceat(absref, starts) if starts.size else np.zeros(0)
+    return 64 * EPS * np.repeat(mx, lens[lens > 0])
+
+
+def check_close(got, ref, absref, what="", cabs=None, row_ptr=None):
     """FP64 bar: |got - ref| <= TOL * S per entry, S the oracle's term-level
-    scale, and the relative Frobenius error <= TOL.  With cabs (the
-    contribution-level scale, sum over cells of |element entry|, which the
-    term-level scale can exceed on near-cancelling entries) the worst error is
-    also reported against it, so that the strength of the bar is visible;
-    returns both worst ratios."""
+    scale, and the relative Frobenius error <= TOL.  For a matrix (row_ptr
+    given) the bar of an entry also has a floor of 64 eps times its row's
+    largest S: where a part of the integrand vanishes identically (the
+    stiffness on an axis-aligned boundary cell) the oracle sums exact zeros
+    while the kernels' metric-form contraction leaves rounding of the row's
+    stiffness size.  With cabs (the contribution-level scale, sum over cells
+    of |element entry|, which the term-level scale can exceed on
+    near-cancelling entries) the worst error is also reported against it, so
+    that the strength of the bar is visible; returns both worst ratios."""
     got = np.asarray(got); ref = np.asarray(ref); absref = np.asarray(absref)
     err = np.abs(got - ref)
-    bad = err > TOL * absref + 1e-300
+    floor = row_floor(absref, row_ptr) if row_ptr is not None else 0.0
+    bad = err > TOL * absref + floor + 1e-300
     w_term = float((err / np.maximum(absref, 1e-300)).max()) if err.size else 0.0
     assert not bad.any(), f"{what}: {bad.sum()} entries outside {TOL}*S; worst {w_term:.3e}"
     nref = np.linalg.norm(ref)

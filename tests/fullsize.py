@@ -79,8 +79,9 @@ def check_sampled_rows(full, nsample=48, seed=12):
     got = np.concatenate([vals[rp[r]:rp[r + 1]] for r in rows])
     for r, (cols, v, a, ca) in zip(rows, ref):
         np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], cols)
+    sub_ptr = np.concatenate([[0], np.cumsum([t[0].size for t in ref])])
     check_close(got, np.concatenate([t[1] for t in ref]), np.concatenate([t[2] for t in ref]),
-                "sampled Mat rows", cabs=np.concatenate([t[3] for t in ref]))
+                "sampled Mat rows", cabs=np.concatenate([t[3] for t in ref]), row_ptr=sub_ptr)
     bs, ba = oracle.vec_rows(dim, deg, d["cells"], d["coords"], d["cn"], d["f"], d["N"], rows)
     check_close(full["b"][rows], bs, ba, "vec")
     ys, ya = oracle.action_rows(dim, deg, d["cells"], d["coords"], d["cn"], d["kappa"], d["x"], d["N"], rows)

@@ -8,18 +8,26 @@ import oracle
 from fem_case import TOL, make_case
 
 
+EPS = 2.0 ** -52
+
+
 def check_rows(got, ref, absref, ptr, what):
-    """Per row: max |gpu - oracle| <= TOL * max_j S_rj, and the Frobenius bar.
-    Pure stiffness blocks have entries whose integrand vanishes identically
-    on axis-aligned boundary cells: the oracle's term scale S is exactly zero
-    there while the metric-form contraction leaves a rounding residue of the
-    order of the row's terms, so the bar is taken row-relative."""
+    """Per entry: |gpu - oracle| <= TOL S_rj + 64 eps max_j S_rj, and the
+    Frobenius bar.  Pure stiffness blocks have entries whose integrand
+    vanishes identically on axis-aligned boundary cells: the oracle's term
+    scale S is exactly zero there while the metric-form contraction leaves
+    rounding of the size of the row's terms (sums of at most 64 of them per
+    cell group), which the second term bounds."""
+    worst = 0.0
     for r in range(len(ptr) - 1):
         a, b = ptr[r], ptr[r + 1]
         if b > a:
-            e = np.max(np.abs(got[a:b] - ref[a:b]))
-            assert e <= TOL * np.max(absref[a:b]) + 1e-300, f"{what}: row {r}"
+            bar = TOL * absref[a:b] + 64 * EPS * np.max(absref[a:b]) + 1e-300
+            e = float(np.max(np.abs(got[a:b] - ref[a:b]) / bar))
+            worst = max(worst, e)
+            assert e <= 1.0, f"{what}: row {r} entry error {e:.3e} of its bar"
     assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref) + 1e-300, f"{what}: Frobenius"
+    print(f"{what}: worst error {worst:.3f} of its bar", flush=True)
 
 pytestmark = pytest.mark.gpu
 

@@ -35,7 +35,7 @@ def test_small_meshes_all_ops(kind, n, deg, layout):
     grp, gci = g.csr()
     np.testing.assert_array_equal(grp, rp)
     np.testing.assert_array_equal(gci, ci)
-    check_close(g.mat(), v, va, "mat")
+    check_close(g.mat(), v, va, "mat", row_ptr=rp)
     check_close(g.vec(), b, ba, "vec")
     check_close(g.action(), y, ya, "action")
 
@@ -46,7 +46,7 @@ def test_other_forms(kind, n, deg, form):
     c = make_case(kind, n, deg)
     g = GpuRun(c, form)
     rp, ci, v, va, _, _, y, ya = _oracle_all(c, form)
-    check_close(g.mat(), v, va, form)
+    check_close(g.mat(), v, va, form, row_ptr=rp)
     check_close(g.action(), y, ya, form + " action")
 
 
@@ -59,7 +59,7 @@ def test_config1_square_p1():
     assert rp[-1] == 7 * 64 * 64 + 6 * 64 + 1
     np.testing.assert_array_equal(grp, rp)
     np.testing.assert_array_equal(gci, ci)
-    check_close(g.mat(), v, va, "mat")
+    check_close(g.mat(), v, va, "mat", row_ptr=rp)
     check_close(g.vec(), b, ba, "vec")
     check_close(g.action(), y, ya, "action")
 
@@ -96,7 +96,7 @@ def test_two_cell_meshes():
             rp, ci, v, va, b, ba, y, ya = _oracle_all(c)
             grp, gci = g.csr()
             np.testing.assert_array_equal(gci, ci)
-            check_close(g.mat(), v, va, "mat")
+            check_close(g.mat(), v, va, "mat", row_ptr=rp)
             check_close(g.vec(), b, ba, "vec")
             check_close(g.action(), y, ya, "action")
 
@@ -116,7 +116,7 @@ def test_isolated_nodes_and_empty_rows():
     grp, gci = g.csr()
     np.testing.assert_array_equal(grp, rp)
     assert rp[-1] == rp[N]
-    check_close(g.mat(), v, va, "mat")
+    check_close(g.mat(), v, va, "mat", row_ptr=rp)
     bb = g.vec()
     check_close(bb, b, ba, "vec")
     assert np.all(bb[N:] == 0)
