@@ -476,8 +476,9 @@ fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args
  * fem_server_poll, which never blocks, retires batches whose work has
  * finished and, while one of the `slots` is free, admits a batch: queued
  * requests taken in admission order (the queue head first, or by
- * fem_server_set_order the smallest) up to fem_server_set_batch's limit (64
- * by default) and as long as each request's outputs fit the HBM budget
+ * fem_server_set_order the smallest) up to fem_server_set_batch's limits (64
+ * requests and a bound on their estimated work by default) and as long as
+ * each request's outputs fit the HBM budget
  * (hbm_budget bytes for resident models plus outputs in flight).  A batch's
  * work is queued on its slot's stream as one persistent launch per kernel
  * (Mat, source vector, action) and (dimension, degree) present, whose
@@ -523,9 +524,14 @@ fem_status fem_server_take_completed(fem_server *server, int64_t *ids, int32_t c
  * launches its persistent Mat kernels on half the compute units, so that it
  * does not shut the others out for its whole duration. */
 fem_status fem_server_configure(fem_server *server, int32_t slots, int32_t share_cus);
-/* Requests per batch, 1..64 (1: every request runs in launches of its own).
- * FEM_E_ARG outside that range. */
-fem_status fem_server_set_batch(fem_server *server, int32_t max_requests);
+/* Batch limits: at most max_requests requests (1..64; 1: every request runs
+ * in launches of its own) and at most max_work of estimated work (the unit
+ * of fem_server_set_order: cell visits times the local tensor size, plus the
+ * Mat values of an assembly; 1e8 by default, about 0.1 ms of an MI355X).  A
+ * request above max_work runs in a batch of its own, so that small requests
+ * batched together do not wait for a large one (a request completes with its
+ * batch).  FEM_E_ARG outside those ranges. */
+fem_status fem_server_set_batch(fem_server *server, int32_t max_requests, double max_work);
 /* Which queued request admission takes next.  FEM_SERVE_FIFO (the default):
  * the queue head.  FEM_SERVE_SHORTEST: the queued request of least estimated
  * work (cell visits of its plan times the local tensor size, plus the Mat

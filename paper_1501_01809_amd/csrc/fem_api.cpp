@@ -162,7 +162,7 @@ fem_status range_check(fem_ctx *ctx, const fem_map *m, int *dflag, const char *n
 
 void free_plan_arrays(fem_plan *p)
 {
-    void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->bnodes, p->inc_ptr, p->ent,
+    void *arrs[] = {p->blk_row0, p->blk_cptr, p->bcell, p->bverts, p->inc_ptr, p->ent,
                     p->blk_hdr, p->blk_w, p->wq, p->pstream,
                     p->e_slot_ptr, p->e_ent, p->e_grow, p->e_work, p->red_partial,
                     p->f_ptr, p->f_ent, p->f_work};
@@ -532,22 +532,6 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     for (int32_t c : hci)
         if (c < 0 || c >= nrows) return fail(ctx, FEM_E_RANGE, "plan_create: a column index lies outside [0, ncols)");
 
-    // P1 Mats whose rows hold at most 64 values take the row-group kernel: a
-    // group of lanes (the row length rounded up to a power of two, at least 8)
-    // per row, the block's element matrices in LDS, the rows' incident cells
-    // as in a Dat plan; no per-contribution schedule.
-    int rg = 0;
-    if (is_mat && deg == 1) {
-        int64_t maxlen = 0;
-        for (int64_t r = 0; r < nrows; ++r) maxlen = std::max<int64_t>(maxlen, hrp[r + 1] - hrp[r]);
-        if (maxlen <= femk::RG_MAX_ROW) {
-            rg = 8;
-            while (rg < maxlen) rg *= 2;
-            lim.cell_cap = femk::rg_cell_cap(dim);
-            lim.rows_per_block = INT32_MAX;
-        }
-    }
-    const bool dat_like = !is_mat || rg > 0;   // entries per row, no value streams
     // Greedy partition of the rows into contiguous blocks bounded by the
     // rows a workgroup owns, the Mat values it can hold in LDS and the
     // distinct cells it can address.  Keep at least ~2 blocks per CU when the
@@ -559,8 +543,8 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     const int lbits = nl <= 4 ? 2 : nl <= 8 ? 3 : nl <= 16 ? 4 : 5;
     std::vector<int32_t> blk_row0{0}, blk_cptr{0}, bcell;
     std::vector<int32_t> stamp(ncells, -1), lpos(ncells, 0);
-    // Dat and row-group plans: packed entries
-    std::vector<uint16_t> hent16(dat_like ? hent.size() : 0);
+    // Dat plans: packed entries
+    std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
     // Mat plans: per-lane LDS index streams (see fem_plan)
     const int MW = is_mat ? lim.lanes : 64, NW = MW / 64;
     const int SCAP = lim.slot_cap, CCH = lim.chunk_cells, NE = lim.ne;
@@ -728,19 +712,12 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         std::sort(bcell.begin() + first_cell, bcell.end());
         const int64_t nc = (int64_t)(bcell.size() - first_cell);
         for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
-        if (dat_like) {
-            for (int64_t r = block_first_row; r < next_row; ++r) {
-                if (rg) {   // every node a row's cells reach must be one of its columns
-                    for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = (int32_t)r;
-                    for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k)
-                        for (int lj = 0; lj < nl; ++lj)
-                            missing |= colmark[hcn[(int64_t)(hent[k] / nl) * nl + lj]] != (int32_t)r;
-                }
+        if (!is_mat) {
+            for (int64_t r = block_first_row; r < next_row; ++r)
                 for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
                     const int32_t e = hent[k];
                     hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
                 }
-            }
         } else {
             mat_streams(next_row, nc);
         }
@@ -752,16 +729,16 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         rows = slots = cells = 0;
     };
     for (int64_t r = 0; r < nrows; ++r) {
-        const int64_t rs = dat_like ? 0 : hrp[r + 1] - hrp[r];
+        const int64_t rs = is_mat ? hrp[r + 1] - hrp[r] : 0;
         int64_t fresh = 0;
         for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) fresh += stamp[hent[k] / nl] != b;
-        if (rows > 0 && (rows + 1 > rows_cap || slots + rs > lim.slot_cap * (int64_t)!dat_like ||
+        if (rows > 0 && (rows + 1 > rows_cap || slots + rs > lim.slot_cap * (int64_t)is_mat ||
                          cells + fresh > lim.cell_cap)) {
             close_block(r);
             fresh = hptr[r + 1] - hptr[r];
         }
         // (a Mat row whose cells exceed one chunk gets a block of several chunks)
-        if ((!dat_like && rs > lim.slot_cap) || (dat_like && fresh > lim.cell_cap))
+        if ((is_mat && rs > lim.slot_cap) || (!is_mat && fresh > lim.cell_cap))
             return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: row %lld is too long for one workgroup",
                         (long long)r);
         for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
@@ -777,7 +754,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     }
     if (rows > 0) close_block(nrows);
     if (missing) return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
-    if (is_mat && !rg) {
+    if (is_mat) {
         wq.push_back((int32_t)(stream.size() / femk::MAT_BATCH));
         if (stream.size() / femk::MAT_BATCH > (size_t)INT32_MAX)
             return fail(ctx, FEM_E_OVERFLOW, "plan_create: Mat streams exceed 2^31 batches");
@@ -808,25 +785,14 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     if (e == hipSuccess) e = upload(p->mem, &p->blk_cptr, blk_cptr, &p->bytes, s);
     if (e == hipSuccess) e = upload(p->mem, &p->bcell, bcell, &p->bytes, s);
     if (e == hipSuccess) e = upload(p->mem, &p->bverts, bverts, &p->bytes, s);
-    p->rg = rg;
-    if (dat_like) {
-        if (!is_mat) {
-            const size_t rb = sizeof(double) * (size_t)femk::reduce_partials(ncells);
-            if (e == hipSuccess) e = femk::mem_alloc(p->mem, s, false, rb ? rb : 8, (void **)&p->red_partial);
-            if (e == hipSuccess) p->bytes += rb;
-        }
+    if (!is_mat) {
+        const size_t rb = sizeof(double) * (size_t)femk::reduce_partials(ncells);
+        if (e == hipSuccess) e = femk::mem_alloc(p->mem, s, false, rb ? rb : 8, (void **)&p->red_partial);
+        if (e == hipSuccess) p->bytes += rb;
         std::vector<int32_t> inc32(nrows + 1);
         for (int64_t r = 0; r <= nrows; ++r) inc32[r] = (int32_t)hptr[r];
         if (e == hipSuccess) e = upload(p->mem, &p->inc_ptr, inc32, &p->bytes, s);
         if (e == hipSuccess) e = upload(p->mem, &p->ent, hent16, &p->bytes, s);
-        // the row-group kernel compares columns with node ids: the vertex ids
-        // serve when the two Maps agree, else the plan keeps the node ids
-        if (rg && !std::equal(hcn.begin(), hcn.end(), hcv.begin())) {
-            std::vector<int32_t> bnodes(bcell.size() * nl);
-            for (size_t i = 0; i < bcell.size(); ++i)
-                for (int m = 0; m < nl; ++m) bnodes[i * nl + m] = hcn[(int64_t)bcell[i] * nl + m];
-            if (e == hipSuccess) e = upload(p->mem, &p->bnodes, bnodes, &p->bytes, s);
-        }
     } else {
         p->nchunks = nchunks;
         p->stream_entries = (int64_t)stream.size();
@@ -937,7 +903,6 @@ fem_status fem_par_loop_assemble_mat(fem_ctx *ctx, const fem_plan *plan, const f
     form_coeffs(form->kind, &a.cstiff, &a.cmass);
     a.coeff = need_k ? args->coeff[0]->data : args->coords->data;   // unread when cstiff == 0
     a.row_ptr = A->sp->row_ptr;
-    a.col_idx = A->sp->col_idx;
     a.out = A->values;
     a.inc = acc == FEM_INC;
     a.num_cus = ctx->num_cus;
@@ -1108,7 +1073,6 @@ fem_status fem_par_loop_assemble_mixed(fem_ctx *ctx, const fem_plan *plan, const
         a.cmass *= bk.scale;
         a.coeff = bk.kind != FEM_MASS ? bk.coeff->data : args->coords->data;   // unread when cstiff == 0
         a.row_ptr = mats[q].sp->row_ptr;
-        a.col_idx = mats[q].sp->col_idx;
         a.out = mats[q].values;
         a.inc = acc == FEM_INC;
         a.num_cus = ctx->num_cus;

@@ -41,7 +41,6 @@ struct KArgs {
     const int32_t *__restrict__ blk_cptr;
     const int32_t *__restrict__ bcell;
     const int32_t *__restrict__ bverts;
-    const int32_t *__restrict__ bnodes;
     const int32_t *__restrict__ inc_ptr;
     const uint16_t *__restrict__ ent;
     const int32_t *__restrict__ blk_hdr;
@@ -49,7 +48,6 @@ struct KArgs {
     const int32_t *__restrict__ wq;
     const uint32_t *__restrict__ pstream;   // batches of MAT_BATCH 16-bit indices
     const int64_t *__restrict__ row_ptr;
-    const int32_t *__restrict__ col_idx;
     const double *__restrict__ coords;
     const int32_t *__restrict__ cell_node;
     const double *__restrict__ coeff;
@@ -63,10 +61,10 @@ KArgs kargs(const AsmArgs &a)
 {
     const fem_plan &p = *a.plan;
     KArgs k;
-    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts; k.bnodes = p.bnodes;
+    k.blk_row0 = p.blk_row0; k.blk_cptr = p.blk_cptr; k.bcell = p.bcell; k.bverts = p.bverts;
     k.inc_ptr = p.inc_ptr; k.ent = p.ent;
     k.blk_hdr = p.blk_hdr; k.blk_w = p.blk_w; k.wq = p.wq; k.pstream = reinterpret_cast<const uint32_t *>(p.pstream);
-    k.row_ptr = a.row_ptr; k.col_idx = a.col_idx; k.coords = a.coords;
+    k.row_ptr = a.row_ptr; k.coords = a.coords;
     k.cell_node = a.cell_node; k.coeff = a.coeff; k.x = a.x; k.out = a.out;
     k.cstiff = a.cstiff; k.cmass = a.cmass; k.inc = a.inc;
     return k;
@@ -580,108 +578,6 @@ __global__ __launch_bounds__((MatCfg<D, K>::WG)) void k_assemble_mat(KArgs a, in
     mat_blocks<D, K>(a, bb, be);
 }
 
-// ---------------------------------------------------------------- P1 Mat by row groups
-
-// P1 matrices have few values per row (7 on triangles, 15 on tetrahedra of a
-// Kuhn mesh) and many cells per value, so a per-contribution schedule costs
-// more bytes than the values.  Instead a group of G lanes owns one row at a
-// time, lane j the row's j-th column: the lanes walk the row's incident cells
-// (the Dat plan's entries, ascending cell id) and each adds the element entry
-// whose column node is its own, found by comparing its column with the
-// cell's vertex ids.  The sum of every value is held in a register, in
-// ascending cell order (the same order, hence the same bits, as the stream
-// kernel), and the row is written once, coalesced.  The block's element
-// matrices and vertex ids live in LDS; a workgroup of RG_WG lanes holds up to
-// RgLds<D>::CMAX cells.
-constexpr int RG_WG = 1024;
-
-template <int D> struct RgLds {
-    static constexpr int NV = D + 1, NE = NV * (NV + 1) / 2;
-    static constexpr int CMAX = (LDS_DOUBLES * 8) / (NE * 8 + NV * 4);
-};
-
-// Packed upper-triangle index of (li, lj) in an element matrix of NV nodes.
-template <int NV>
-__device__ __forceinline__ int upper_idx(int li, int lj)
-{
-    const int i = min(li, lj), j = max(li, lj);
-    return i * (2 * NV - i + 1) / 2 + (j - i);
-}
-
-template <int D, int G>
-__device__ __forceinline__ void mat_rg_block(const KArgs &a, int b)
-{
-    using L = RgLds<D>;
-    constexpr int NV = L::NV, NE = L::NE, CM = L::CMAX, NG = RG_WG / G;
-    static_assert(NE == TabOf<D, 1>::T::NE, "packed P1 element matrix");
-    __shared__ double e_lds[CM * NE];
-    __shared__ int32_t v_lds[CM * NV];
-    const int tid = threadIdx.x;
-    const int r0 = a.blk_row0[b], r1 = a.blk_row0[b + 1];
-    const int c0 = a.blk_cptr[b], nc = a.blk_cptr[b + 1] - c0;
-    // 1. the block's cells: vertex ids and element matrices into LDS (the
-    //    next pass's gather is in flight while a pass computes)
-    // (the node ids the columns are compared with are the vertex ids when the
-    // plan found the two Maps equal, else the plan's per-visit node ids)
-    CellIn<D> cin;
-    int32_t vid[NV], nid[NV];
-    auto fetch = [&](int c) {
-#pragma unroll
-        for (int m = 0; m < NV; ++m) vid[m] = a.bverts[(int64_t)(c0 + c) * NV + m];
-        issue_coords<D>(vid, a.coords, a.coeff, cin);
-        if (a.bnodes) {
-#pragma unroll
-            for (int m = 0; m < NV; ++m) nid[m] = a.bnodes[(int64_t)(c0 + c) * NV + m];
-        } else {
-#pragma unroll
-            for (int m = 0; m < NV; ++m) nid[m] = vid[m];
-        }
-    };
-    if (tid < nc) fetch(tid);
-    for (int cs = 0; cs < nc; cs += RG_WG) {
-        const int c = cs + tid;
-        if (c < nc) {
-            double E[NE];
-            cell_tensor<D, 1>(0, cin, a.cstiff, a.cmass, E);
-#pragma unroll
-            for (int q = 0; q < NE; ++q) e_lds[c * NE + q] = E[q];
-#pragma unroll
-            for (int m = 0; m < NV; ++m) v_lds[c * NV + m] = nid[m];
-        }
-        if (c + RG_WG < nc) fetch(c + RG_WG);
-    }
-    lds_barrier();
-    // 2. rows: group g takes rows r0 + g, r0 + g + NG, ...; lane j its j-th column
-    const int g = tid / G, j = tid % G;
-    for (int r = r0 + g; r < r1; r += NG) {
-        const int64_t p0 = a.row_ptr[r];
-        const int len = (int)(a.row_ptr[r + 1] - p0);
-        const int32_t col = j < len ? a.col_idx[p0 + j] : -1;
-        const int e0 = a.inc_ptr[r], e1 = a.inc_ptr[r + 1];
-        double acc = -0.0;
-        for (int eb = e0; eb < e1; eb += G) {
-            // G entries at once, one per lane, then broadcast in the group
-            const uint32_t mine = eb + j < e1 ? (uint32_t)a.ent[eb + j] : 0u;
-            const int ne = min(G, e1 - eb);
-            for (int k = 0; k < ne; ++k) {
-                const uint32_t w = (uint32_t)__shfl((int)mine, k, G);
-                const int lc = (int)(w >> 2), li = (int)(w & 3u);
-                int lj = -1;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) lj = v_lds[lc * NV + m] == col ? m : lj;
-                if (lj >= 0) acc += e_lds[lc * NE + upper_idx<NV>(li, lj)];
-            }
-        }
-        if (j < len) a.out[p0 + j] = a.inc ? a.out[p0 + j] + acc : acc;
-    }
-}
-
-template <int D, int G>
-__global__ __launch_bounds__(RG_WG) void k_mat_rg(KArgs a)
-{
-    mat_rg_block<D, G>(a, blockIdx.x);
-}
-
 // ---------------------------------------------------------------- Dat / action
 
 template <int D, int K, bool ACTION>
@@ -776,25 +672,9 @@ __global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_assemble_vec(KArg
     vec_block<D, K, ACTION>(a, blockIdx.x);
 }
 
-template <int D>
-hipError_t rg_dispatch(const AsmArgs &a, hipStream_t s)
-{
-    const dim3 grid(a.plan->nblk), block(RG_WG);
-    switch (a.plan->rg) {
-    case 8: hipLaunchKernelGGL((k_mat_rg<D, 8>), grid, block, 0, s, kargs(a)); break;
-    case 16: hipLaunchKernelGGL((k_mat_rg<D, 16>), grid, block, 0, s, kargs(a)); break;
-    case 32: hipLaunchKernelGGL((k_mat_rg<D, 32>), grid, block, 0, s, kargs(a)); break;
-    case 64: hipLaunchKernelGGL((k_mat_rg<D, 64>), grid, block, 0, s, kargs(a)); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 template <int D, int K>
 hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 {
-    if constexpr (K == 1)
-        if (a.plan->rg) return rg_dispatch<D>(a, s);
     const int nblk = a.plan->nblk;
     const int grid = std::min(nblk, std::max(a.num_cus, 1));
     hipLaunchKernelGGL((k_assemble_mat<D, K>), dim3(grid), dim3(MatCfg<D, K>::WG), 0, s, kargs(a), nblk);
@@ -802,8 +682,6 @@ hipError_t mat_dispatch(const AsmArgs &a, hipStream_t s)
 }
 
 }  // namespace
-
-int rg_cell_cap(int dim) { return dim == 2 ? RgLds<2>::CMAX : RgLds<3>::CMAX; }
 
 bool limits(int dim, int degree, bool is_mat, Limits *out)
 {
@@ -925,17 +803,6 @@ __global__ __launch_bounds__((VecWG<D, K, ACTION>::WG)) void k_vec_batch(BatchHd
     }
 }
 
-template <int D, int G>
-__global__ __launch_bounds__(RG_WG) void k_mat_rg_batch(BatchHdr *hdr, const int32_t *prefix, const KArgs *reqs)
-{
-    int it;
-    while (batch_item(hdr, it)) {
-        const int r = batch_request(prefix, it);
-        const KArgs a = load_kargs(reqs + r);
-        mat_rg_block<D, G>(a, it - ldc(prefix + r));
-    }
-}
-
 constexpr int BATCH_BPI = 8;   // Mat blocks per work item (pipelined within the item)
 
 struct BatchLayout {
@@ -950,26 +817,12 @@ struct BatchLayout {
 };
 
 template <int D, int K>
-hipError_t batch_dispatch(int op, int rg, int grid, char *desc, const BatchLayout &L, int total, hipStream_t s)
+hipError_t batch_dispatch(int op, int grid, char *desc, const BatchLayout &L, int total, hipStream_t s)
 {
     BatchHdr *hdr = reinterpret_cast<BatchHdr *>(desc);
     const int32_t *prefix = reinterpret_cast<const int32_t *>(desc + L.prefix);
     const int32_t *nblk = reinterpret_cast<const int32_t *>(desc + L.nblk);
     const KArgs *reqs = reinterpret_cast<const KArgs *>(desc + L.reqs);
-    if (op == 0 && rg) {
-        if constexpr (K == 1) {
-            const dim3 g(std::min(grid, total)), b(RG_WG);
-            switch (rg) {
-            case 8: hipLaunchKernelGGL((k_mat_rg_batch<D, 8>), g, b, 0, s, hdr, prefix, reqs); break;
-            case 16: hipLaunchKernelGGL((k_mat_rg_batch<D, 16>), g, b, 0, s, hdr, prefix, reqs); break;
-            case 32: hipLaunchKernelGGL((k_mat_rg_batch<D, 32>), g, b, 0, s, hdr, prefix, reqs); break;
-            case 64: hipLaunchKernelGGL((k_mat_rg_batch<D, 64>), g, b, 0, s, hdr, prefix, reqs); break;
-            default: return hipErrorInvalidValue;
-            }
-            return hipGetLastError();
-        }
-        return hipErrorInvalidValue;
-    }
     if (op == 0) {
         hipLaunchKernelGGL((k_mat_batch<D, K>), dim3(std::min(grid, total)), dim3(MatCfg<D, K>::WG), 0, s, hdr,
                            prefix, nblk, reqs);
@@ -992,8 +845,7 @@ hipError_t launch_batch(int op, const AsmArgs *reqs, int nreq, int grid, void *h
     if (nreq <= 0) return hipSuccess;
     const fem_plan &p0 = *reqs[0].plan;
     for (int r = 0; r < nreq; ++r)
-        if (reqs[r].plan->dim != p0.dim || reqs[r].plan->degree != p0.degree || reqs[r].plan->is_mat != (op == 0) ||
-            reqs[r].plan->rg != p0.rg)
+        if (reqs[r].plan->dim != p0.dim || reqs[r].plan->degree != p0.degree || reqs[r].plan->is_mat != (op == 0))
             return hipErrorInvalidValue;
     const BatchLayout L(nreq);
     char *h = static_cast<char *>(hdesc);
@@ -1002,7 +854,7 @@ hipError_t launch_batch(int op, const AsmArgs *reqs, int nreq, int grid, void *h
     int32_t *prefix = reinterpret_cast<int32_t *>(h + L.prefix);
     int32_t *nblk = reinterpret_cast<int32_t *>(h + L.nblk);
     KArgs *ka = reinterpret_cast<KArgs *>(h + L.reqs);
-    const int bpi = op == 0 && !p0.rg ? BATCH_BPI : 1;   // one block per item for the one-block kernels
+    const int bpi = op == 0 ? BATCH_BPI : 1;
     prefix[0] = 0;
     for (int r = 0; r < nreq; ++r) {
         nblk[r] = reqs[r].plan->nblk;
@@ -1019,12 +871,12 @@ hipError_t launch_batch(int op, const AsmArgs *reqs, int nreq, int grid, void *h
     const int total = hdr->total;
     char *d = static_cast<char *>(desc);
     switch (p0.dim * 10 + p0.degree) {
-    case 21: return batch_dispatch<2, 1>(op, p0.rg, grid, d, L, total, s);
-    case 22: return batch_dispatch<2, 2>(op, p0.rg, grid, d, L, total, s);
-    case 23: return batch_dispatch<2, 3>(op, p0.rg, grid, d, L, total, s);
-    case 31: return batch_dispatch<3, 1>(op, p0.rg, grid, d, L, total, s);
-    case 32: return batch_dispatch<3, 2>(op, p0.rg, grid, d, L, total, s);
-    case 33: return batch_dispatch<3, 3>(op, p0.rg, grid, d, L, total, s);
+    case 21: return batch_dispatch<2, 1>(op, grid, d, L, total, s);
+    case 22: return batch_dispatch<2, 2>(op, grid, d, L, total, s);
+    case 23: return batch_dispatch<2, 3>(op, grid, d, L, total, s);
+    case 31: return batch_dispatch<3, 1>(op, grid, d, L, total, s);
+    case 32: return batch_dispatch<3, 2>(op, grid, d, L, total, s);
+    case 33: return batch_dispatch<3, 3>(op, grid, d, L, total, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -59,7 +59,6 @@ struct fem_plan {
     int64_t stream_entries = 0;  // Mat plans: 16-bit stream entries (padding included)
     int64_t cell_visits = 0;     // sum over blocks of cells gathered
     int32_t max_blk_cells = 0;   // most cells any block gathers
-    int rg = 0;                  // P1 Mat plans: lanes per row group (8..64), 0: value streams
     double *red_partial = nullptr;  // Dat plans: one partial per 1024 cells (Global reductions)
     // Exterior facet plans (is_mat == 3; ncells = facets): node-to-facet
     // incidence (entries f*nloc + l, ascending) and the facet vectors.
@@ -83,7 +82,6 @@ struct fem_plan {
     int32_t *blk_cptr = nullptr;  // [nblk+1] offsets into bcell
     int32_t *bcell = nullptr;     // ascending global cell ids of each block
     int32_t *bverts = nullptr;    // [visits][dim+1] vertex ids of each bcell entry
-    int32_t *bnodes = nullptr;    // P1 row-group plans whose node Map differs from the vertex Map: node ids
     int32_t *inc_ptr = nullptr;   // Dat plans: [nrows+1] entry range of each row
     uint16_t *ent = nullptr;      // Dat plans: (local cell << lbits) | local index
     int32_t *blk_hdr = nullptr;   // Mat plans: [nblk][8] block header (layout in fem_assemble.hip)
@@ -148,7 +146,6 @@ struct AsmArgs {
     const double *coeff;     // kappa (bilinear) or f (source)
     double cstiff, cmass;
     const int64_t *row_ptr;
-    const int32_t *col_idx;  // Mat: the sparsity's columns (P1 row-group kernel)
     const double *x;         // action input; u of the nonlinear residual
     const double *aux;       // nonlinear residual: f (residual) or lambda (adjoint)
     double *out;             // Mat values / Dat
@@ -202,9 +199,6 @@ struct Limits {
     int lanes;              // Mat: lanes of the workgroup (the streams are dealt to them)
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
-// Cells a P1 row-group Mat block holds (its element matrices and vertex ids in LDS).
-int rg_cell_cap(int dim);
-// Largest row of the P1 row-group Mat kernel (lanes of a group).
-constexpr int RG_MAX_ROW = 64;
+
 
 }  // namespace femk

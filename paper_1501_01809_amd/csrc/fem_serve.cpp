@@ -129,7 +129,7 @@ struct Arena {
 // Requests of one batch (at most FEM_SERVE_MAX_BATCH), and the descriptor
 // memory of its launches: one (op, dimension, degree) group per launch.
 constexpr int FEM_SERVE_MAX_BATCH = 64;
-constexpr int FEM_SERVE_GROUPS = 26;     // 3 kernels x 6 (dimension, degree), P1 Mats by 4 row-group widths
+constexpr int FEM_SERVE_GROUPS = 18;     // 3 kernels x 6 (dimension, degree)
 
 struct fem_server {
     fem_ctx *ctx = nullptr;
@@ -138,6 +138,7 @@ struct fem_server {
     int active = 0;                       // slots admission may use (<= streams.size())
     int share_cus = 1;                    // halve the Mat launch's grid while others run
     int max_batch = FEM_SERVE_MAX_BATCH;  // requests per batch
+    double max_work = 1e8;                // estimated work per batch (a larger request runs alone)
     int order = FEM_SERVE_FIFO;           // which queued request admission takes next
     double max_wait = 0;                  // FEM_SERVE_SHORTEST: a head waiting this long goes first
     std::vector<hipStream_t> streams;
@@ -314,7 +315,7 @@ static fem_status launch_batch_on(fem_server *s, int slot, const std::vector<int
 {
     fem_ctx *ctx = s->ctx;
     hipStream_t st = s->streams[slot];
-    // group: kernel (op), dimension and degree, and for P1 Mats the row-group width
+    // group: kernel (op), dimension and degree
     std::map<int, std::vector<femk::AsmArgs>> groups;
     for (int64_t rid : batch) {
         const Request &r = s->reqs[rid];
@@ -329,16 +330,15 @@ static fem_status launch_batch_on(fem_server *s, int slot, const std::vector<int
         const int dk = ((int)m.form.cell - 2) * 3 + (m.form.degree - 1);
         if (r.op == FEM_REQ_ASSEMBLE) {
             femk::AsmArgs am = a;
-            am.plan = m.mplan; am.coeff = m.kappa.data; am.row_ptr = m.sp.row_ptr; am.col_idx = m.sp.col_idx;
-            am.out = r.values;
-            groups[(0 * 6 + dk) * 128 + m.mplan->rg].push_back(am);
+            am.plan = m.mplan; am.coeff = m.kappa.data; am.row_ptr = m.sp.row_ptr; am.out = r.values;
+            groups[0 * 6 + dk].push_back(am);
             femk::AsmArgs av = a;
             av.plan = m.vplan; av.coeff = m.f.data; av.out = r.vec;
-            groups[(1 * 6 + dk) * 128].push_back(av);
+            groups[1 * 6 + dk].push_back(av);
         } else {
             femk::AsmArgs aa = a;
             aa.plan = m.vplan; aa.coeff = m.kappa.data; aa.x = r.x; aa.out = r.vec;
-            groups[(2 * 6 + dk) * 128].push_back(aa);
+            groups[2 * 6 + dk].push_back(aa);
         }
     }
     // the Mat launch fills every CU while its work lasts; while other batches
@@ -347,7 +347,7 @@ static fem_status launch_batch_on(fem_server *s, int slot, const std::vector<int
     const int mat_grid = busy && s->share_cus ? (cus > 1 ? cus / 2 : 1) : cus;
     size_t off = 0;
     for (auto &kv : groups) {
-        const int op = kv.first / 128 / 6;
+        const int op = kv.first / 6;
         const std::vector<femk::AsmArgs> &gr = kv.second;
         char *h = static_cast<char *>(s->hdesc[slot]) + off, *d = static_cast<char *>(s->ddesc[slot]) + off;
         SHIP(femk::launch_batch(op, gr.data(), (int)gr.size(), op == 0 ? mat_grid : cus, h, d, st),
@@ -395,6 +395,7 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
             if (s->slot_reqs[k].empty()) { slot = k; break; }
         if (slot < 0) break;
         std::vector<int64_t> batch;
+        double batch_work = 0.0;
         while (!s->queue.empty() && (int)batch.size() < s->max_batch) {
             auto pick = s->queue.begin();
             if (s->order == FEM_SERVE_SHORTEST && now - s->reqs[*pick].t_arrival < s->max_wait)
@@ -402,6 +403,7 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
                     if (s->reqs[*it].work < s->reqs[*pick].work) pick = it;
             const int64_t rid = *pick;
             Request &r = s->reqs[rid];
+            if (!batch.empty() && batch_work + r.work > s->max_work) break;
             if (s->resident + s->in_use + r.bytes > s->budget) break;
             const Model &m = *s->models[r.model];
             // outputs from the arena (fragmentation may refuse what the
@@ -421,6 +423,7 @@ fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_
             s->in_use += r.bytes;
             s->queue.erase(pick);
             batch.push_back(rid);
+            batch_work += r.work;
         }
         if (batch.empty()) break;
         bool busy = !s->queue.empty();
@@ -490,12 +493,14 @@ fem_status fem_server_configure(fem_server *s, int32_t slots, int32_t share_cus)
     return FEM_OK;
 }
 
-fem_status fem_server_set_batch(fem_server *s, int32_t max_requests)
+fem_status fem_server_set_batch(fem_server *s, int32_t max_requests, double max_work)
 {
     if (!s) return FEM_E_ARG;
     if (max_requests < 1 || max_requests > FEM_SERVE_MAX_BATCH)
         return sfail(s->ctx, FEM_E_ARG, "set_batch: 1..%d requests per batch", FEM_SERVE_MAX_BATCH);
+    if (!(max_work > 0)) return sfail(s->ctx, FEM_E_ARG, "set_batch: max_work must be positive");
     s->max_batch = max_requests;
+    s->max_work = max_work;
     return FEM_OK;
 }
 

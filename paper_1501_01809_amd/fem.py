@@ -153,7 +153,7 @@ def lib():
         L.fem_server_release.argtypes = [P, C.c_int64]
         L.fem_server_configure.argtypes = [P, C.c_int32, C.c_int32]
         L.fem_server_set_order.argtypes = [P, C.c_int32, C.c_double]
-        L.fem_server_set_batch.argtypes = [P, C.c_int32]
+        L.fem_server_set_batch.argtypes = [P, C.c_int32, C.c_double]
         L.fem_server_take_completed.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_server_model_info.argtypes = [P, C.c_int32, I64p, I64p, I64p, C.POINTER(P), C.POINTER(P)]
         for name in EXPORTS:
@@ -555,9 +555,10 @@ class Server:
     def configure(self, slots: int, share_cus: bool = True):
         self.ctx.check(lib().fem_server_configure(self.h, slots, int(share_cus)))
 
-    def set_batch(self, max_requests: int):
-        """Requests per batch (1: each request in launches of its own)."""
-        self.ctx.check(lib().fem_server_set_batch(self.h, max_requests))
+    def set_batch(self, max_requests: int, max_work: float = 1e8):
+        """Requests per batch (1: each request in launches of its own) and the
+        estimated work a batch may hold (a larger request runs alone)."""
+        self.ctx.check(lib().fem_server_set_batch(self.h, max_requests, max_work))
 
     def set_order(self, order: int, max_wait: float = 0.0):
         """FEM_SERVE_FIFO or FEM_SERVE_SHORTEST (least estimated work first; a

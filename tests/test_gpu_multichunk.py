@@ -1,16 +1,14 @@
-"""GPU parity of Mat plans whose row blocks hold more cells than one pass.
+"""GPU parity of Mat plans whose row blocks hold several chunks of cells.
 
-A P2/P3 Mat block keeps its values in LDS while chunks of its cells pass
-through (chunk sizes per dimension and degree below); the kernel pipelines
-the next chunk's data behind the current one and the plan balances the lane
-streams chunk by chunk.  A P1 block (the row-group kernel) computes its
-cells' element matrices in passes of 1024, one per lane.  The small parity
-cases fit in one chunk or pass per block.  Here the cells and nodes are
-numbered at random (a block's rows then share few cells) and the meshes are
-sized so that the blocks hold several chunks or passes (checked from the
-plan: mean cells per block above one); the whole CSR is compared with the
-oracle, entry by entry (1e-12 of the term scale), plus bitwise run-to-run
-reproducibility.
+A Mat block keeps its values in LDS while chunks of its cells pass through
+(chunk sizes per dimension and degree below); the kernel pipelines the next
+chunk's data behind the current one and the plan balances the lane streams
+chunk by chunk.  The small parity cases fit in one chunk per block.  Here the
+cells and nodes are numbered at random (a block's rows then share few cells)
+and the meshes are sized so that the blocks hold several chunks (checked
+from the plan: mean cells per block above one chunk); the whole CSR is
+compared with the oracle, entry by entry (1e-12 of the term scale), plus
+bitwise run-to-run reproducibility.
 """
 import numpy as np
 import pytest
@@ -20,8 +18,8 @@ from fem_case import GpuRun, check_close, make_case
 
 pytestmark = pytest.mark.gpu
 
-# (mesh, n, degree, cells of one chunk or pass)
-CASES = [("square", 400, 1, 1024), ("cube", 40, 1, 1024), ("cube", 14, 2, 256),
+# (mesh, n, degree, cells of one chunk)
+CASES = [("square", 400, 1, 512), ("cube", 40, 1, 512), ("cube", 14, 2, 256),
          ("square", 80, 3, 128), ("cube", 8, 3, 32)]
 
 

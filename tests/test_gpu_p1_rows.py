@@ -1,7 +1,8 @@
-"""P1 matrices take the row-group kernel when every row holds at most 64
-values and the value-stream kernel otherwise; both against the oracle, with
-cell-to-node and cell-to-vertex Maps that differ (node ids compared with the
-columns are then the plan's own) and that agree."""
+"""P1 matrices on meshes with long rows and with node Maps that differ from
+the vertex Map: fans of 40, 63 and 100 triangles around one vertex (rows of
+41 to 101 values, whose cells span several lanes' streams), and shuffled
+meshes whose cell-to-node Map is a renumbering of the cell-to-vertex Map,
+against the oracle and bitwise run to run."""
 import numpy as np
 import pytest
 

@@ -114,7 +114,7 @@ def test_alone_equals_mix_and_oracle():
     # batches of up to 8 requests: mixed meshes, degrees and operations share
     # launches, and batches overlap
     F2, ctx2, srv8, models8 = _server(8, 8 << 30)
-    srv8.set_batch(8)
+    srv8.set_batch(8, 1e12)                               # no work bound: the whole mix in 8-request batches
     rids, mm, oo = [], {}, {}
     for p, op in seq:
         q = models8[p["id"]]
@@ -192,9 +192,9 @@ def test_admission_respects_the_budget_and_slots():
 def test_server_rejections():
     F, ctx, srv, models = _server(2, 4 << 30, SPECS[:1])
     p = models[0]
-    for bad in (0, 65):
+    for bad, work in ((0, 1e8), (65, 1e8), (4, 0.0)):
         with pytest.raises(F.FemError) as e:
-            srv.set_batch(bad)
+            srv.set_batch(bad, work)
         assert e.value.status == F.FEM_E_ARG
     with pytest.raises(F.FemError) as e:
         srv.submit(5, F.FEM_REQ_ASSEMBLE)
@@ -242,4 +242,26 @@ def test_shortest_first_order():
         assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
     for a, b in ((fs, ss), (fs, hs)):
         assert np.array_equal(a[1].view(np.uint64), b[1].view(np.uint64))
+    srv.close()
+
+
+def test_batch_work_bound():
+    """A batch closes before a request that would take its estimated work
+    past the bound; that request then runs in a batch of its own."""
+    F, ctx, srv, models = _server(1, 8 << 30)
+    small, big = models[0], models[5]          # a P1 triangle action, a P3 tetrahedron assembly
+    # an action's estimated work: its Dat plan's cell visits times nloc^2 (the
+    # server's plan is built the same way on the same device)
+    g = small["g"]
+    vplan = F.fem_plan_create(ctx, F.form("helmholtz", 2, 1), F.Args(g["cv"], g["X"], g["cn"], small["N"],
+                                                                     [g["kappa"]]), None)
+    w_small = vplan.info()["cell_visits"] * 9
+    srv.set_batch(64, 2.5 * w_small)           # two small actions fit, a third or the large assembly not
+    seq = [(small, F.FEM_REQ_ACTION), (small, F.FEM_REQ_ACTION), (big, F.FEM_REQ_ASSEMBLE),
+           (small, F.FEM_REQ_ACTION)]
+    rids = [srv.submit(p["id"], op, p["g"]["x"] if op == F.FEM_REQ_ACTION else None) for p, op in seq]
+    _, running, queued = srv.poll(0.0)
+    assert (running, queued) == (2, 2), "the batch closes before the large request"
+    res = _drain(srv, F, rids, dict(zip(rids, [p for p, _ in seq])), dict(zip(rids, [op for _, op in seq])))
+    assert res[rids[2]][2] > res[rids[0]][2], "the large request is admitted in a later batch"
     srv.close()
