@@ -120,14 +120,19 @@ __device__ __forceinline__ T ldc(const T *p)
 // P, which keeps fewer values live.  All measured per case: MT paid
 // everywhere but on P3 triangles (P2 tetrahedra 510 -> 463 us); 1024 lanes
 // paid on triangles of degree 2 and 3 (16 waves hide more latency) and lost
-// on tetrahedra, whose shorter per-lane streams pad more.
+// on tetrahedra, whose shorter per-lane streams pad more.  The element
+// tensors take every wave only if CCH LPC reaches WG with a part that is the
+// same across each wave (CCH a multiple of 64): P3 tetrahedra went from 32
+// cells x 4 lanes (two of eight waves evaluating, 5.2 ms) to 64 cells x 8
+// lanes (2.96 ms), although the larger chunk halves the value area and
+// raises the redundancy from 3.37 to 4.09.
 template <int D, int K> struct MatCfg;
 template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 2, MCH = 1, WG = 1024, NB = 4; static constexpr bool MT = true; };
 template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 2, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4, WG = 1024, NB = 4; static constexpr bool MT = false; };
-template <> struct MatCfg<3, 3> { static constexpr int CCH = 32, LPC = 4, MCH = 8, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
+template <> struct MatCfg<3, 3> { static constexpr int CCH = 64, LPC = 8, MCH = 8, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 
 // Dat and action kernels: workgroups of WG lanes, KR rows per lane; the
 // per-cell local vectors of the whole block live in LDS (VLDS doubles, two
@@ -269,26 +274,25 @@ __device__ __forceinline__ void issue_coords(const int32_t (&v)[D + 1], const do
     }
 }
 
-// Entry groups [g0, g0 + NG/LPC) of a cell's packed element tensor.
+// Entry groups [part NG/LPC, (part + 1) NG/LPC) of a cell's packed element
+// tensor.  The common splits call the groups by name; others go through the
+// numbered dispatch (a uniform branch when the part is the same on a wave).
 template <class T, int LPC>
 __device__ __forceinline__ void mat_part(int part, const double *P, double madet, double *E)
 {
+    static_assert(T::NG % LPC == 0, "entry groups per lane");
     if constexpr (T::NG == 1) {
         T::mat_group0(P, madet, E);
-    } else if constexpr (LPC == 1) {
+    } else if constexpr (T::NG == 4 && LPC == 1) {
         T::mat_group0(P, madet, E); T::mat_group1(P, madet, E);
         T::mat_group2(P, madet, E); T::mat_group3(P, madet, E);
-    } else if constexpr (LPC == 2) {
+    } else if constexpr (T::NG == 4 && LPC == 2) {
         if (part == 0) { T::mat_group0(P, madet, E); T::mat_group1(P, madet, E); }
         else { T::mat_group2(P, madet, E); T::mat_group3(P, madet, E); }
     } else {
-        static_assert(LPC == 4, "lanes per cell");
-        switch (part) {
-        case 0: T::mat_group0(P, madet, E); break;
-        case 1: T::mat_group1(P, madet, E); break;
-        case 2: T::mat_group2(P, madet, E); break;
-        default: T::mat_group3(P, madet, E); break;
-        }
+        constexpr int GPL = T::NG / LPC;
+#pragma unroll
+        for (int i = 0; i < GPL; ++i) T::mat_group_n(part * GPL + i, P, madet, E);
     }
 }
 
@@ -296,22 +300,19 @@ __device__ __forceinline__ void mat_part(int part, const double *P, double madet
 template <class T, int LPC>
 __device__ __forceinline__ void mat_part_t(int part, const double *kc, const double *G, double madet, double *E)
 {
+    static_assert(T::NG % LPC == 0, "entry groups per lane");
     if constexpr (T::NG == 1) {
         T::mat_group_t0(kc, G, madet, E);
-    } else if constexpr (LPC == 1) {
+    } else if constexpr (T::NG == 4 && LPC == 1) {
         T::mat_group_t0(kc, G, madet, E); T::mat_group_t1(kc, G, madet, E);
         T::mat_group_t2(kc, G, madet, E); T::mat_group_t3(kc, G, madet, E);
-    } else if constexpr (LPC == 2) {
+    } else if constexpr (T::NG == 4 && LPC == 2) {
         if (part == 0) { T::mat_group_t0(kc, G, madet, E); T::mat_group_t1(kc, G, madet, E); }
         else { T::mat_group_t2(kc, G, madet, E); T::mat_group_t3(kc, G, madet, E); }
     } else {
-        static_assert(LPC == 4, "lanes per cell");
-        switch (part) {
-        case 0: T::mat_group_t0(kc, G, madet, E); break;
-        case 1: T::mat_group_t1(kc, G, madet, E); break;
-        case 2: T::mat_group_t2(kc, G, madet, E); break;
-        default: T::mat_group_t3(kc, G, madet, E); break;
-        }
+        constexpr int GPL = T::NG / LPC;
+#pragma unroll
+        for (int i = 0; i < GPL; ++i) T::mat_group_tn(part * GPL + i, kc, G, madet, E);
     }
 }
 

@@ -286,6 +286,19 @@ def emit(d, k, G):
                 expr = f"G[{t}] * ({dot})" if expr is None else f"__builtin_fma(G[{t}], ({dot}), {expr})"
             out.append(f"    E[{upper_index(i, j, n)}] = {expr if expr else '0.0'};")
         out.append("  }")
+    # entry group g by number (a switch: uniform when g is the same on a wave)
+    out.append("  __device__ __forceinline__ static void mat_group_n(int g, const double* __restrict__ P, double madet, double* __restrict__ E) {")
+    out.append("    switch (g) {")
+    for g in range(G):
+        out.append(f"    {'default' if g == G - 1 else f'case {g}'}: mat_group{g}(P, madet, E); break;")
+    out.append("    }")
+    out.append("  }")
+    out.append("  __device__ __forceinline__ static void mat_group_tn(int g, const double* __restrict__ kc, const double* __restrict__ G, double madet, double* __restrict__ E) {")
+    out.append("    switch (g) {")
+    for g in range(G):
+        out.append(f"    {'default' if g == G - 1 else f'case {g}'}: mat_group_t{g}(kc, G, madet, E); break;")
+    out.append("    }")
+    out.append("  }")
     out.append("  // upper triangle, row-major (i<=j), Eu[NE]")
     out.append("  __device__ __forceinline__ static void mat_upper(const double* __restrict__ P, double madet, double* __restrict__ Eu) {")
     u = 0
@@ -322,6 +335,12 @@ def emit(d, k, G):
     return "\n".join(out), nterms
 
 
+# Entry groups per element tensor (one lane of a cell evaluates NG/LPC of
+# them).  P1 tensors are one group; P3 tetrahedra are split into 8 so that
+# eight lanes share a cell's 210 entries.
+GROUPS = {(2, 1): 1, (3, 1): 1, (3, 3): 8}
+
+
 def main(path):
     parts = ["// Generated by gen_tables.py -- exact reference integrals of Lagrange P1-P3",
              "// bases (see the generator's docstring for the formulas).  Do not edit.",
@@ -329,7 +348,7 @@ def main(path):
     summary = []
     for d in (2, 3):
         for k in (1, 2, 3):
-            G = 1 if k == 1 else 4
+            G = GROUPS.get((d, k), 4)
             code, nt = emit(d, k, G)
             parts.append(code)
             summary.append((d, k, nt))
