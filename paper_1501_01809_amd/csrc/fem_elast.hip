@@ -284,24 +284,55 @@ __global__ __launch_bounds__(256) void k_elast_pull(const int64_t *__restrict__ 
     double acc[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) acc[u] = 0.0;
-    const int t1 = slot_ptr[e + 1];
-    for (int t = slot_ptr[e]; t < t1; ++t) {
-        const uint32_t w = ent[t];
-        const T *blk = E + (size_t)(w >> 8) * BLK + ((w >> 2) & 63) * 9;
+    const int t0 = slot_ptr[e], t1 = slot_ptr[e + 1];
+    // software pipeline over the contributions: the entry word two ahead and
+    // the 3x3 block one ahead are in flight while a block is added.  The
+    // look-ahead indices are clamped to the slot's last contribution, so the
+    // loads need no branch (a branch around them makes the compiler wait for
+    // every load in flight before the adds).
+    if (t0 < t1) {
+        auto block_of = [&](uint32_t w) { return E + (size_t)(w >> 8) * BLK + ((w >> 2) & 63) * 9; };
+        const int tl = t1 - 1;
+        uint32_t w0 = ent[t0];
+        uint32_t w1 = ent[min(t0 + 1, tl)];
         T v[9];
+        {
+            const T *blk = block_of(w0);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) v[q] = blk[q];
-        const bool dg = (w >> 1) & 1, tr = w & 1;
+            for (int q = 0; q < 9; ++q) v[q] = blk[q];
+        }
+        for (int t = t0; t < t1; ++t) {
+            const uint32_t w2 = ent[min(t + 2, tl)];
+            T vn[9];
+            const T *blk = block_of(w1);
 #pragma unroll
-        for (int x = 0; x < 3; ++x)
+            for (int q = 0; q < 9; ++q) vn[q] = blk[q];
+            double d[9];
 #pragma unroll
-            for (int y = 0; y < 3; ++y) {
-                // entry (x, y) of the block is v[x][y], or v[y][x] when
-                // transposed; on the diagonal the upper triangle serves both
-                // halves (bitwise symmetric sums)
-                const bool take_b = x > y ? (dg || tr) : (x < y ? (tr && !dg) : false);
-                acc[x * 3 + y] += (double)(take_b ? v[y * 3 + x] : v[x * 3 + y]);
+            for (int q = 0; q < 9; ++q) {
+                d[q] = (double)v[q];
+                asm volatile("" : "+v"(d[q]));   // nine values, not an array indexed at run time
             }
+            // entry (x, y) is d[x][y], or d[y][x] when transposed; on the
+            // diagonal the upper triangle serves both halves (bitwise
+            // symmetric sums): below the diagonal the mirror is taken when
+            // diagonal or transposed, above it when transposed only
+            const bool dg = (w0 >> 1) & 1, tr = w0 & 1;
+            const bool lo = dg || tr, up = tr && !dg;
+            acc[0] += d[0];
+            acc[4] += d[4];
+            acc[8] += d[8];
+            acc[3] += lo ? d[1] : d[3];
+            acc[1] += up ? d[3] : d[1];
+            acc[6] += lo ? d[2] : d[6];
+            acc[2] += up ? d[6] : d[2];
+            acc[7] += lo ? d[5] : d[7];
+            acc[5] += up ? d[7] : d[5];
+            w0 = w1;
+            w1 = w2;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) v[q] = vn[q];
+        }
     }
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
