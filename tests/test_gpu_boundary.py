@@ -1,7 +1,8 @@
 """The boundary's memory, versioning and quadrature contract, through the C
 ABI: device memory from the caller's allocator (counted), caller-provided
 sparsity scratch (query, then provide), Map versions that invalidate plans,
-the quadrature degree, and the sparsity's row-length limit as a status code."""
+the quadrature degree, and the row-length limits of the sparsity build and
+of the Mat and Dat plans as status codes."""
 import numpy as np
 import pytest
 
@@ -151,3 +152,75 @@ def test_row_candidate_limit_is_a_status():
     sp = F.fem_build_sparsity(ctx, torch.from_numpy(tri).cuda(), m + 1)
     rp, ci = oracle.sparsity(tri, m + 1)
     assert np.array_equal(sp.row_ptr.cpu().numpy(), rp) and np.array_equal(sp.col_idx.cpu().numpy(), ci)
+
+
+def test_mat_row_longer_than_the_value_area_is_a_status():
+    """A caller's CSR may hold more entries than the Maps reach.  A P2
+    tetrahedron row whose CSR row is dense (9,261 columns, beyond the 6,392
+    values a block's LDS holds) makes plan creation report FEM_E_UNSUPPORTED;
+    the same sparsity with row 0 cut back to its mesh columns plus a few
+    extra ones builds, and the extra entries assemble to zero."""
+    import torch
+    from paper_1501_01809_amd import fem as F
+    c = make_case("cube", 10, 2)
+    g = GpuRun(c)
+    N = c.nnodes
+    rp, ci = oracle.sparsity(c.cell_node, N)
+    assert N > 6392
+
+    def with_row0(cols0):
+        cols = [np.asarray(cols0, dtype=np.int32)] + [ci[rp[r]:rp[r + 1]] for r in range(1, N)]
+        lens = np.array([len(x) for x in cols], dtype=np.int64)
+        row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        return F.Sparsity(torch.from_numpy(row_ptr).cuda(), torch.from_numpy(np.concatenate(cols)).cuda(), N, N), \
+            row_ptr, np.concatenate(cols)
+
+    sp, _, _ = with_row0(np.arange(N))
+    with pytest.raises(F.FemError) as e:
+        F.fem_plan_create(g.ctx, g.form, g.args_k, sp)
+    assert e.value.status == F.FEM_E_UNSUPPORTED and "too long" in str(e.value)
+    extra = np.union1d(ci[rp[0]:rp[1]], np.arange(N - 40, N))
+    sp2, rp2, ci2 = with_row0(extra)
+    plan = F.fem_plan_create(g.ctx, g.form, g.args_k, sp2)
+    vals = torch.zeros(ci2.size, dtype=torch.float64, device="cuda")
+    F.fem_par_loop_assemble_mat(g.ctx, plan, g.form, g.args_k, vals, sp2)
+    F.fem_sync(g.ctx)
+    got = vals.cpu().numpy()
+    v, va = oracle.assemble_mat(c.dim, 2, c.cells, c.coords, c.cell_node, c.kappa, rp2, ci2)
+    check_close(got, v, va, "mat with extra row-0 entries", row_ptr=rp2)
+    mesh_cols = set(ci[rp[0]:rp[1]].tolist())
+    assert all(got[k] == 0.0 for k in range(rp2[0], rp2[1]) if ci2[k] not in mesh_cols)
+
+
+def test_dat_row_with_more_cells_than_a_block_holds_is_a_status():
+    """A vertex with 4,000 triangles around it: its row's incident cells do
+    not fit a Dat block's LDS (3,413 P1 triangles), so plan creation reports
+    FEM_E_UNSUPPORTED; 3,000 triangles fit and the source vector matches the
+    oracle."""
+    import torch
+    from paper_1501_01809_amd import fem as F
+    ctx = F.Context(0)
+
+    def fan(n):
+        t = np.arange(n)
+        tri = np.stack([np.zeros(n, dtype=np.int32), 1 + t, 1 + (t + 1) % n], 1).astype(np.int32)
+        ang = 2 * np.pi * t / n
+        X = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+        f = np.linspace(-1.0, 1.0, n + 1)
+        return tri, np.ascontiguousarray(X), f
+
+    tri, X, f = fan(4000)
+    dt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = F.Args(dt(tri), dt(X), dt(tri), tri.shape[0] + 1, [dt(f)])
+    src = F.form("source", 2, 1)
+    with pytest.raises(F.FemError) as e:
+        F.fem_plan_create(ctx, src, args, None)
+    assert e.value.status == F.FEM_E_UNSUPPORTED and "too long" in str(e.value)
+    tri, X, f = fan(3000)
+    args = F.Args(dt(tri), dt(X), dt(tri), tri.shape[0] + 1, [dt(f)])
+    plan = F.fem_plan_create(ctx, src, args, None)
+    b = torch.zeros(tri.shape[0] + 1, dtype=torch.float64, device="cuda")
+    F.fem_par_loop_assemble_vec(ctx, plan, src, args, b)
+    F.fem_sync(ctx)
+    want, wabs = oracle.assemble_vec(2, 1, tri, X, tri, f, tri.shape[0] + 1)
+    check_close(b.cpu().numpy(), want, wabs, "vec on a 3000-triangle fan")

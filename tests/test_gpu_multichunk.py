@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 # (mesh, n, degree, cells of one chunk)
 CASES = [("square", 400, 1, 512), ("cube", 40, 1, 512), ("cube", 14, 2, 256),
-         ("square", 80, 3, 128), ("cube", 8, 3, 32)]
+         ("square", 80, 3, 128), ("cube", 8, 3, 64)]
 
 
 @pytest.mark.parametrize("kind,n,deg,chunk", CASES)
