@@ -156,8 +156,12 @@ constexpr int VPRE = 8;     // entries of a row fetched per batch
 // registers).  PREFETCH gathers the next cell's inputs while the current one
 // is evaluated; the P2 tetrahedron drops it to stay within 128 VGPRs (four
 // waves per SIMD), which measured 125 against 153 us at 64^3 x 6 cells.
+// QUAD (P2): the stiffness part at the points of an exact degree-3 rule
+// (act_q; about 380 instead of 835 FMAs per P2 tetrahedron), the mass part
+// from the exact reference mass matrix.
 template <int D, int K> struct ActCfg {
     static constexpr bool METRIC = K <= 2;
+    static constexpr bool QUAD = K == 2;
     static constexpr bool PREFETCH = !(D == 3 && K == 2);
 };
 
@@ -625,7 +629,8 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
                     const double adet = Geo<D>::metric(cin.x, G);
 #pragma unroll
                     for (int m = 0; m <= D; ++m) kc[m] = a.cstiff * cin.k[m];
-                    T::act_t(kc, G, a.cmass * adet, xl, loc);
+                    if constexpr (ActCfg<D, K>::QUAD) T::act_q(kc, G, a.cmass * adet, xl, loc);
+                    else T::act_t(kc, G, a.cmass * adet, xl, loc);
                 } else {
                     double P[NP], madet;
                     tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);

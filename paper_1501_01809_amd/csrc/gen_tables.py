@@ -237,6 +237,116 @@ def emit_act_t(d, n, NM, stiff, mass):
     return out
 
 
+# Degree-3 rules on the reference simplex, as (weight, barycentric point)
+# with the weights summing to 1 (the integral over the reference simplex is
+# the weighted sum divided by d!): the tetrahedron's five-point rule (centroid
+# weight -4/5, four points (1/2, 1/6, 1/6, 1/6) of weight 9/20) and the
+# triangle's four-point rule (centroid -9/16, three points (3/5, 1/5, 1/5) of
+# weight 25/48).  Both are checked below to integrate every monomial of
+# degree <= 3 exactly.
+def _perms(pt):
+    return sorted(set(itertools.permutations(pt)))
+
+
+QRULES = {
+    3: [(Fraction(-4, 5), (Fraction(1, 4),) * 4)] +
+       [(Fraction(9, 20), p) for p in _perms((Fraction(1, 2), Fraction(1, 6), Fraction(1, 6), Fraction(1, 6)))],
+    2: [(Fraction(-9, 16), (Fraction(1, 3),) * 3)] +
+       [(Fraction(25, 48), p) for p in _perms((Fraction(3, 5), Fraction(1, 5), Fraction(1, 5)))],
+}
+
+
+def check_rule(d, rule, degree=3):
+    nv = d + 1
+    for tot in range(degree + 1):
+        for a in itertools.product(range(tot + 1), repeat=nv):
+            if sum(a) != tot:
+                continue
+            q = sum(w * poly_eval({a: Fraction(1)}, pt) for w, pt in rule)
+            assert q == factorial(d) * integrate({a: Fraction(1)}, d), f"rule not exact for {a}"
+
+
+def poly_eval(p, pt):
+    s = Fraction(0)
+    for a, c in p.items():
+        t = c
+        for x, e in zip(pt, a):
+            t *= x ** e
+        s += t
+    return s
+
+
+def emit_act_q(d, k):
+    """y += A x for one P2 cell with the stiffness part evaluated at the
+    points of a degree-3 rule, which is exact for its integrand (P1 kappa
+    times two gradients of P2 functions), and the mass part from the exact
+    reference mass matrix:
+
+      y_i += sum_q (w_q / d!) kappa(q) sum_m d_m phi_i(q) sum_n G[mn] a_n(q)
+             + madet sum_j Mref_ij x_j,   a_n(q) = sum_j d_n phi_j(q) x_j
+
+    with kappa(q) = sum_k kc[k] l_k(q).  About 380 FMAs per P2 tetrahedron
+    against 835 for act_t; the result equals the exact integral up to
+    rounding."""
+    assert k == 2
+    nv = d + 1
+    rule = QRULES[d]
+    check_rule(d, rule)
+    B = basis(d, k)
+    n = len(B)
+    dB = [[poly_d(B[i], m) for m in range(nv)] for i in range(n)]
+    pairs = metric_pairs(nv)
+    gidx = {}
+    for t, (m, q) in enumerate(pairs):
+        gidx[(m, q)] = gidx[(q, m)] = t
+    mass = {(i, j): integrate(poly_mul(B[i], B[j]), d) for i in range(n) for j in range(n)}
+    out = ["  // y += A x for one cell: stiffness at the points of an exact degree-3 rule,",
+           "  // mass from the exact reference mass matrix (kc = cstiff kappa, G = metric)",
+           "  __device__ __forceinline__ static void act_q(const double* __restrict__ kc, const double* __restrict__ G, double madet, const double* __restrict__ x, double* __restrict__ y) {"]
+    for i in range(n):
+        expr = None
+        for j in range(n):
+            w = mass[(i, j)]
+            if w == 0:
+                continue
+            expr = f"{hexlit(w)} * x[{j}]" if expr is None else f"__builtin_fma({hexlit(w)}, x[{j}], {expr})"
+        out.append(f"    y[{i}] = __builtin_fma(madet, {expr}, y[{i}]);")
+    for qi, (w, pt) in enumerate(rule):
+        sc = w / factorial(d)
+        out.append("    {")
+        kexpr = None
+        for kk in range(nv):
+            cf = sc * pt[kk]
+            kexpr = f"{hexlit(cf)} * kc[{kk}]" if kexpr is None else f"__builtin_fma({hexlit(cf)}, kc[{kk}], {kexpr})"
+        out.append(f"      const double kq = {kexpr};")
+        for m in range(nv):
+            expr = None
+            for j in range(n):
+                cf = poly_eval(dB[j][m], pt)
+                if cf == 0:
+                    continue
+                expr = f"{hexlit(cf)} * x[{j}]" if expr is None else f"__builtin_fma({hexlit(cf)}, x[{j}], {expr})"
+            out.append(f"      const double a{m} = {expr if expr else '0.0'};")
+        for m in range(nv):
+            expr = None
+            for q in range(nv):
+                g = f"G[{gidx[(m, q)]}]"
+                expr = f"{g} * a{q}" if expr is None else f"__builtin_fma({g}, a{q}, {expr})"
+            out.append(f"      const double c{m} = kq * ({expr});")
+        for i in range(n):
+            expr = f"y[{i}]"
+            for m in range(nv):
+                cf = poly_eval(dB[i][m], pt)
+                if cf == 0:
+                    continue
+                expr = f"__builtin_fma({hexlit(cf)}, c{m}, {expr})"
+            if expr != f"y[{i}]":
+                out.append(f"      y[{i}] = {expr};")
+        out.append("    }")
+    out.append("  }")
+    return out
+
+
 def emit(d, k, G):
     n, pairs, stiff, mass, src = tables(d, k)
     nv = d + 1
@@ -322,6 +432,8 @@ def emit(d, k, G):
             out.append("    }")
     out.append("  }")
     out.extend(emit_act_t(d, n, NM, stiff, mass))
+    if k == 2:
+        out.extend(emit_act_q(d, k))
     out.append("  // b_i = adet * sum_k f_k int l_k phi_i")
     out.append("  __device__ __forceinline__ static void vec(const double* __restrict__ f, double adet, double* __restrict__ b) {")
     for i in range(n):
