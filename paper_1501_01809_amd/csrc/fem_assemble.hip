@@ -616,6 +616,18 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
             for (int j = 0; j < NL; ++j) xl[j] = a.x[a.cell_node[cell * NL + j]];
         }
     };
+    // each row's entry range: for the source vector loaded at once (two
+    // registers, in flight during the cell phase), for the action after it
+    int cur[KR], end[KR];
+    auto row_range = [&]() {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int r = r0 + tid + WG * k;
+            cur[k] = r < r1 ? a.inc_ptr[r] : 0;
+            end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
+        }
+    };
+    if constexpr (!ACTION) row_range();
     if (PRE && tid < nc) fetch(tid);
     for (int cs = 0; cs < nc; cs += WG) {
         if (cs + tid < nc) {
@@ -646,14 +658,11 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
     }
     // the rows' first entries are fetched only now, so that they hold no
     // registers while the cells are evaluated
-    int cur[KR], end[KR];
     uint32_t pe[KR][VPRE];
     double acc[KR];
+    if constexpr (ACTION) row_range();
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
-        const int r = r0 + tid + WG * k;
-        cur[k] = r < r1 ? a.inc_ptr[r] : 0;
-        end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
         acc[k] = 0.0;
 #pragma unroll
         for (int m = 0; m < VPRE; ++m) pe[k][m] = cur[k] + m < end[k] ? a.ent[cur[k] + m] : 0u;
