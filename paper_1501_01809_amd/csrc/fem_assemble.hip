@@ -156,12 +156,13 @@ constexpr int VPRE = 8;     // entries of a row fetched per batch
 // registers).  PREFETCH gathers the next cell's inputs while the current one
 // is evaluated; the P2 tetrahedron drops it to stay within 128 VGPRs (four
 // waves per SIMD), which measured 125 against 153 us at 64^3 x 6 cells.
-// QUAD (P2): the stiffness part at the points of an exact degree-3 rule
-// (act_q; about 380 instead of 835 FMAs per P2 tetrahedron), the mass part
-// from the exact reference mass matrix.
+// QUAD (P2, P3): the stiffness part at the points of a rule exact for its
+// degree (act_q: degree 3 for P2, about 380 instead of 835 FMAs per P2
+// tetrahedron; degree 5 for P3, 15 points on the tetrahedron), the mass
+// part from the exact reference mass matrix.
 template <int D, int K> struct ActCfg {
-    static constexpr bool METRIC = K <= 2;
-    static constexpr bool QUAD = K == 2;
+    static constexpr bool METRIC = true;
+    static constexpr bool QUAD = K >= 2;
     static constexpr bool PREFETCH = !(D == 3 && K == 2);
 };
 
@@ -616,8 +617,8 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
             for (int j = 0; j < NL; ++j) xl[j] = a.x[a.cell_node[cell * NL + j]];
         }
     };
-    // each row's entry range: for the source vector loaded at once (two
-    // registers, in flight during the cell phase), for the action after it
+    // each row's entry range, loaded at once (two registers, in flight
+    // during the cell phase)
     int cur[KR], end[KR];
     auto row_range = [&]() {
 #pragma unroll
@@ -627,7 +628,7 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
             end[k] = r < r1 ? a.inc_ptr[r + 1] : 0;
         }
     };
-    if constexpr (!ACTION) row_range();
+    row_range();
     if (PRE && tid < nc) fetch(tid);
     for (int cs = 0; cs < nc; cs += WG) {
         if (cs + tid < nc) {
@@ -657,10 +658,10 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
         if (PRE && cs + WG + tid < nc) fetch(cs + WG + tid);
     }
     // the rows' first entries are fetched only now, so that they hold no
-    // registers while the cells are evaluated
+    // registers while the cells are evaluated (one round trip: the ranges
+    // have arrived)
     uint32_t pe[KR][VPRE];
     double acc[KR];
-    if constexpr (ACTION) row_range();
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         acc[k] = 0.0;

@@ -256,6 +256,24 @@ QRULES = {
 }
 
 
+def gm_rule(d, s):
+    """Grundmann-Moeller rule of degree 2s+1 on the d-simplex (rational
+    points and weights, some negative): level i = 0..s contributes the
+    points with barycentric coordinates (2 beta_j + 1) / (2s+1 + d - 2i),
+    |beta| = s - i, with weight proportional to
+    (-1)^i (2s+1 + d - 2i)^(2s+1) / (i! (2s+1 + d - i)!); the weights are
+    normalised to sum to 1."""
+    deg = 2 * s + 1
+    rule = []
+    for i in range(s + 1):
+        w = Fraction((-1) ** i * (deg + d - 2 * i) ** deg, 2 ** (2 * s) * factorial(i) * factorial(deg + d - i))
+        for beta in itertools.product(range(s - i + 1), repeat=d + 1):
+            if sum(beta) == s - i:
+                rule.append((w, tuple(Fraction(2 * b + 1, deg + d - 2 * i) for b in beta)))
+    tot = sum(w for w, _ in rule)
+    return [(w / tot, pt) for w, pt in rule]
+
+
 def check_rule(d, rule, degree=3):
     nv = d + 1
     for tot in range(degree + 1):
@@ -277,9 +295,10 @@ def poly_eval(p, pt):
 
 
 def emit_act_q(d, k):
-    """y += A x for one P2 cell with the stiffness part evaluated at the
-    points of a degree-3 rule, which is exact for its integrand (P1 kappa
-    times two gradients of P2 functions), and the mass part from the exact
+    """y += A x for one cell with the stiffness part evaluated at the points
+    of a rule exact for its integrand (P1 kappa times two gradients of
+    degree k-1: degree 2k-1; the rules above for P2, the degree-5
+    Grundmann-Moeller rule for P3), and the mass part from the exact
     reference mass matrix:
 
       y_i += sum_q (w_q / d!) kappa(q) sum_m d_m phi_i(q) sum_n G[mn] a_n(q)
@@ -288,10 +307,10 @@ def emit_act_q(d, k):
     with kappa(q) = sum_k kc[k] l_k(q).  About 380 FMAs per P2 tetrahedron
     against 835 for act_t; the result equals the exact integral up to
     rounding."""
-    assert k == 2
+    assert k in (2, 3)
     nv = d + 1
-    rule = QRULES[d]
-    check_rule(d, rule)
+    rule = QRULES[d] if k == 2 else gm_rule(d, 2)
+    check_rule(d, rule, 2 * k - 1)
     B = basis(d, k)
     n = len(B)
     dB = [[poly_d(B[i], m) for m in range(nv)] for i in range(n)]
@@ -300,7 +319,7 @@ def emit_act_q(d, k):
     for t, (m, q) in enumerate(pairs):
         gidx[(m, q)] = gidx[(q, m)] = t
     mass = {(i, j): integrate(poly_mul(B[i], B[j]), d) for i in range(n) for j in range(n)}
-    out = ["  // y += A x for one cell: stiffness at the points of an exact degree-3 rule,",
+    out = [f"  // y += A x for one cell: stiffness at the points of an exact degree-{2 * k - 1} rule,",
            "  // mass from the exact reference mass matrix (kc = cstiff kappa, G = metric)",
            "  __device__ __forceinline__ static void act_q(const double* __restrict__ kc, const double* __restrict__ G, double madet, const double* __restrict__ x, double* __restrict__ y) {"]
     for i in range(n):
@@ -432,7 +451,7 @@ def emit(d, k, G):
             out.append("    }")
     out.append("  }")
     out.extend(emit_act_t(d, n, NM, stiff, mass))
-    if k == 2:
+    if k >= 2:
         out.extend(emit_act_q(d, k))
     out.append("  // b_i = adet * sum_k f_k int l_k phi_i")
     out.append("  __device__ __forceinline__ static void vec(const double* __restrict__ f, double adet, double* __restrict__ b) {")
