@@ -149,19 +149,17 @@ template <int D, int K, bool ACTION> struct VecWG {
 };
 constexpr int VLDS = LDS_DOUBLES / 2;
 constexpr int VPRE = 8;     // entries of a row fetched per batch
-// Action: METRIC evaluates y_K = A_K x_K from the cstiff-scaled nodal kappa
-// and the metric, terms grouped by metric pair (act_t), instead of from the
-// (d+1) x NM products P (act): fewer live registers, a few more FMAs.  It
-// pays for P1 and P2 and not for P3 (the inner sums then crowd out the
-// registers).  PREFETCH gathers the next cell's inputs while the current one
-// is evaluated; the P2 tetrahedron drops it to stay within 128 VGPRs (four
-// waves per SIMD), which measured 125 against 153 us at 64^3 x 6 cells.
+// Action: y_K = A_K x_K from the cstiff-scaled nodal kappa and the metric.
+// P1: terms grouped by metric pair (act_t), rather than formed from the
+// (d+1) x NM products P, which keeps fewer registers live.  PREFETCH gathers
+// the next cell's inputs while the current one is evaluated; the P2
+// tetrahedron drops it to stay within 128 VGPRs (four waves per SIMD),
+// which measured 125 against 153 us at 64^3 x 6 cells.
 // QUAD (P2, P3): the stiffness part at the points of a rule exact for its
 // degree (act_q: degree 3 for P2, about 380 instead of 835 FMAs per P2
 // tetrahedron; degree 5 for P3, 15 points on the tetrahedron), the mass
-// part from the exact reference mass matrix.
+// part from the exact reference mass matrix; P1 keeps act_t.
 template <int D, int K> struct ActCfg {
-    static constexpr bool METRIC = true;
     static constexpr bool QUAD = K >= 2;
     static constexpr bool PREFETCH = !(D == 3 && K == 2);
 };
@@ -637,18 +635,12 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
             if constexpr (ACTION) {
 #pragma unroll
                 for (int j = 0; j < NL; ++j) loc[j] = 0.0;
-                if constexpr (ActCfg<D, K>::METRIC) {
-                    double G[Geo<D>::NM], kc[D + 1];
-                    const double adet = Geo<D>::metric(cin.x, G);
+                double G[Geo<D>::NM], kc[D + 1];
+                const double adet = Geo<D>::metric(cin.x, G);
 #pragma unroll
-                    for (int m = 0; m <= D; ++m) kc[m] = a.cstiff * cin.k[m];
-                    if constexpr (ActCfg<D, K>::QUAD) T::act_q(kc, G, a.cmass * adet, xl, loc);
-                    else T::act_t(kc, G, a.cmass * adet, xl, loc);
-                } else {
-                    double P[NP], madet;
-                    tensor_inputs<D>(cin, a.cstiff, a.cmass, P, &madet);
-                    T::act(P, madet, xl, loc);
-                }
+                for (int m = 0; m <= D; ++m) kc[m] = a.cstiff * cin.k[m];
+                if constexpr (ActCfg<D, K>::QUAD) T::act_q(kc, G, a.cmass * adet, xl, loc);
+                else T::act_t(kc, G, a.cmass * adet, xl, loc);
             } else {
                 T::vec(cin.k, Geo<D>::absdet(cin.x), loc);
             }

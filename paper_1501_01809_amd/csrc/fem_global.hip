@@ -86,20 +86,11 @@ __global__ __launch_bounds__(RWG) void k_reduce_cells(RedArgs a)
             double xl[NL], y[NL];
 #pragma unroll
             for (int i = 0; i < NL; ++i) { xl[i] = a.x[a.cell_node[c * NL + i]]; y[i] = 0.0; }
-            if constexpr (K <= 2) {
-                // terms grouped by metric pair: fewer live registers (P1, P2)
-                double kc[NV];
+            double kc[NV];
 #pragma unroll
-                for (int m = 0; m < NV; ++m) kc[m] = a.cstiff * k[m];
-                Tab::act_t(kc, G, a.cmass * adet, xl, y);
-            } else {
-                double P[NV * NM];
-#pragma unroll
-                for (int m = 0; m < NV; ++m)
-#pragma unroll
-                    for (int t = 0; t < NM; ++t) P[m * NM + t] = a.cstiff * k[m] * G[t];
-                Tab::act(P, a.cmass * adet, xl, y);
-            }
+            for (int m = 0; m < NV; ++m) kc[m] = a.cstiff * k[m];
+            if constexpr (K == 1) Tab::act_t(kc, G, a.cmass * adet, xl, y);   // terms grouped by metric pair
+            else Tab::act_q(kc, G, a.cmass * adet, xl, y);   // stiffness at the points of an exact rule
 #pragma unroll
             for (int i = 0; i < NL; ++i) q = __builtin_fma(xl[i], y[i], q);
         } else {
