@@ -598,7 +598,6 @@ __device__ __forceinline__ void vec_block(const KArgs &a, int b)
     constexpr int WG = VecWG<D, K, ACTION>::WG, KR = VecWG<D, K, ACTION>::KR;
     using T = typename TabOf<D, K>::T;
     constexpr int NL = T::NLOC, LB = lbits_for(NL);
-    constexpr int NP = (D + 1) * Geo<D>::NM;
     constexpr int CAP = VLDS / NL;
     __shared__ double vk[CAP * NL];
     const int tid = threadIdx.x;
