@@ -125,11 +125,17 @@ __device__ __forceinline__ T ldc(const T *p)
 // same across each wave (CCH a multiple of 64): P3 tetrahedra went from 32
 // cells x 4 lanes (two of eight waves evaluating, 5.2 ms) to 64 cells x 8
 // lanes (2.96 ms), although the larger chunk halves the value area and
-// raises the redundancy from 3.37 to 4.09.
+// raises the redundancy from 3.37 to 4.09.  P1 takes 1,024-cell chunks on
+// 1,024 lanes (116 VGPRs on tetrahedra): each lane's stream per chunk is as
+// long as with 512 and 512 but half the blocks' chunk boundaries, and 16
+// waves hide more latency (P1 triangles 2048^2 241 -> 182 us, tetrahedra
+// 64^3 83 -> 73 us, 128^3 619 -> 594 us with a smaller value area).  P2
+// triangles fill the 1,024 lanes with 512-cell chunks (189 -> 184 us at
+// 1024^2, against 384-cell chunks on 768 lanes).
 template <int D, int K> struct MatCfg;
-template <> struct MatCfg<2, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 4, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
-template <> struct MatCfg<3, 1> { static constexpr int CCH = 512, LPC = 1, MCH = 16, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
-template <> struct MatCfg<2, 2> { static constexpr int CCH = 384, LPC = 2, MCH = 1, WG = 1024, NB = 4; static constexpr bool MT = true; };
+template <> struct MatCfg<2, 1> { static constexpr int CCH = 1024, LPC = 1, MCH = 2, WG = 1024, NB = 4; static constexpr bool MT = true; };
+template <> struct MatCfg<3, 1> { static constexpr int CCH = 1024, LPC = 1, MCH = 8, WG = 1024, NB = 4; static constexpr bool MT = true; };
+template <> struct MatCfg<2, 2> { static constexpr int CCH = 512, LPC = 2, MCH = 1, WG = 1024, NB = 4; static constexpr bool MT = true; };
 template <> struct MatCfg<3, 2> { static constexpr int CCH = 256, LPC = 2, MCH = 2, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };
 template <> struct MatCfg<2, 3> { static constexpr int CCH = 128, LPC = 4, MCH = 4, WG = 1024, NB = 4; static constexpr bool MT = false; };
 template <> struct MatCfg<3, 3> { static constexpr int CCH = 64, LPC = 8, MCH = 8, WG = 512, NB = 64 / MAT_BATCH; static constexpr bool MT = true; };

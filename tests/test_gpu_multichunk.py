@@ -19,7 +19,7 @@ from fem_case import GpuRun, check_close, make_case
 pytestmark = pytest.mark.gpu
 
 # (mesh, n, degree, cells of one chunk)
-CASES = [("square", 400, 1, 512), ("cube", 40, 1, 512), ("cube", 14, 2, 256),
+CASES = [("square", 400, 1, 1024), ("cube", 40, 1, 1024), ("cube", 14, 2, 256),
          ("square", 80, 3, 128), ("cube", 8, 3, 64)]
 
 
