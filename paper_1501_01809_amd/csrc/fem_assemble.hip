@@ -120,7 +120,8 @@ __device__ __forceinline__ T ldc(const T *p)
 // P, which keeps fewer values live.  All measured per case: MT paid
 // everywhere but on P3 triangles (P2 tetrahedra 510 -> 463 us); 1024 lanes
 // paid on triangles of degree 2 and 3 (16 waves hide more latency) and lost
-// on tetrahedra, whose shorter per-lane streams pad more.  The element
+// on P2 tetrahedra, where the chunk cannot grow with them and the shorter
+// per-lane streams pad more.  The element
 // tensors take every wave only if CCH LPC reaches WG with a part that is the
 // same across each wave (CCH a multiple of 64): P3 tetrahedra went from 32
 // cells x 4 lanes (two of eight waves evaluating, 5.2 ms) to 64 cells x 8
