@@ -19,7 +19,8 @@
 // scaled per cell by a power of two (exact) that brings its entries to
 // magnitude <= 1, and the FP32 accumulator is scaled back; accumulation is in
 // FP32 (FP64 for the FP64 path).  The blocks (i <= j, 3 x 3 each) go to a
-// plan-owned workspace E[cell][pair][a*3+b].
+// plan-owned workspace E[cell][pair][a*3+b] (FP64; FP32 for the FP32 and FP16
+// contractions; bfloat16, padded to ten values per block, for BF16).
 //
 // Stage 2, k_elast_pull: one lane per node pair (i, j) of the node sparsity,
 // a 3 x 3 block of the vector CSR.  The lane walks the plan's list of
@@ -43,7 +44,6 @@ namespace {
 constexpr int NL = femelast::NLOC;        // 10 local nodes
 constexpr int NP = femelast::NPAIR;       // 55 upper node pairs
 constexpr int NQ = femelast::NQ;          // 36 contraction terms
-constexpr int BLK = NP * 9;               // workspace values per cell
 constexpr int EWG = 256;                  // element kernel: 4 waves
 constexpr int CPW = 16;                   // cells per wave and group
 
@@ -86,6 +86,56 @@ template <> struct Mf<FEM_FP16> {
     static constexpr int KS = 3, KP = 4;
     static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
     static __device__ __forceinline__ Acc mma(In a, In b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+};
+
+// Workspace element: FP64 and FP32 blocks of nine values; BF16 contractions
+// store their blocks as bfloat16 bits, nine values and one pad (20-byte,
+// 4-byte aligned blocks: the pull reads one with a 16-byte and a 4-byte
+// load instead of three), which halves the workspace; FP16 keeps FP32 (its
+// outputs are not kept in FP16 range by the operand scaling).
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+template <typename W> struct Ws;
+template <> struct Ws<double> { static constexpr int BS = 9; };
+template <> struct Ws<float> { static constexpr int BS = 9; };
+template <> struct Ws<uint16_t> { static constexpr int BS = 10; };
+template <int P> struct WsOf { typedef float T; };
+template <> struct WsOf<FEM_FP64> { typedef double T; };
+template <> struct WsOf<FEM_BF16> { typedef uint16_t T; };
+__device__ __forceinline__ void ws_put(double *E, double v) { *E = v; }
+__device__ __forceinline__ void ws_put(float *E, float v) { *E = v; }
+__device__ __forceinline__ void ws_put(uint16_t *E, float v) { *E = (uint16_t)f2bf(v); }
+__device__ __forceinline__ double bf2d(uint32_t bits16) { return (double)__uint_as_float(bits16 << 16); }
+// One block as loaded (raw, so that a block loaded ahead is not waited for
+// until it is used), and its nine values as doubles.
+template <typename W> struct Blk {
+    W v[9];
+    __device__ __forceinline__ void load(const W *b)
+    {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] = b[q];
+    }
+    __device__ __forceinline__ void get(double (&d)[9]) const
+    {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) d[q] = (double)v[q];
+    }
+};
+template <> struct Blk<uint16_t> {
+    u32x4a w;
+    uint32_t w4;
+    __device__ __forceinline__ void load(const uint16_t *b)
+    {
+        w = *reinterpret_cast<const u32x4a *>(b);
+        w4 = *reinterpret_cast<const uint32_t *>(b + 8);
+    }
+    __device__ __forceinline__ void get(double (&d)[9]) const
+    {
+        d[0] = bf2d(w.x & 0xffffu); d[1] = bf2d(w.x >> 16);
+        d[2] = bf2d(w.y & 0xffffu); d[3] = bf2d(w.y >> 16);
+        d[4] = bf2d(w.z & 0xffffu); d[5] = bf2d(w.z >> 16);
+        d[6] = bf2d(w.w & 0xffffu); d[7] = bf2d(w.w >> 16);
+        d[8] = bf2d(w4 & 0xffffu);
+    }
 };
 
 // Pack KP values of one lane's K slice into the MFMA operand type.
@@ -144,8 +194,9 @@ __global__ __launch_bounds__(EWG) void k_elast_element(ElArgs a)
             }
             afr[mt][ks] = pack<P>(t);
         }
-    typedef typename M::Out Out;
-    Out *E = reinterpret_cast<Out *>(a.work);
+    typedef typename WsOf<P>::T W;
+    constexpr int BS = Ws<W>::BS;
+    W *E = reinterpret_cast<W *>(a.work);
     const int64_t ngroups = (a.ncells + CPW - 1) / CPW;
     // every wave of a workgroup runs the same number of iterations (barriers)
     for (int64_t g0 = (int64_t)blockIdx.x * (EWG / 64); g0 < ngroups; g0 += (int64_t)gridDim.x * (EWG / 64)) {
@@ -255,7 +306,7 @@ __global__ __launch_bounds__(EWG) void k_elast_element(ElArgs a)
                 for (int v = 0; v < 4; ++v) {
                     const int pr = 16 * mt + M::row(lane, v);
                     if (live && pr < NP)
-                        E[cell * BLK + pr * 9 + ab] = (Out)(acc[v] * (typename M::Out)scale);
+                        ws_put(E + cell * (NP * BS) + pr * BS + ab, acc[v] * (typename M::Out)scale);
                 }
             }
         }
@@ -291,28 +342,21 @@ __global__ __launch_bounds__(256) void k_elast_pull(const int64_t *__restrict__ 
     // loads need no branch (a branch around them makes the compiler wait for
     // every load in flight before the adds).
     if (t0 < t1) {
-        auto block_of = [&](uint32_t w) { return E + (size_t)(w >> 8) * BLK + ((w >> 2) & 63) * 9; };
+        constexpr int BS = Ws<T>::BS;
+        auto block_of = [&](uint32_t w) { return E + (size_t)(w >> 8) * (NP * BS) + ((w >> 2) & 63) * BS; };
         const int tl = t1 - 1;
         uint32_t w0 = ent[t0];
         uint32_t w1 = ent[min(t0 + 1, tl)];
-        T v[9];
-        {
-            const T *blk = block_of(w0);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) v[q] = blk[q];
-        }
+        Blk<T> v;
+        v.load(block_of(w0));
         for (int t = t0; t < t1; ++t) {
             const uint32_t w2 = ent[min(t + 2, tl)];
-            T vn[9];
-            const T *blk = block_of(w1);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) vn[q] = blk[q];
+            Blk<T> vn;
+            vn.load(block_of(w1));
             double d[9];
+            v.get(d);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                d[q] = (double)v[q];
-                asm volatile("" : "+v"(d[q]));   // nine values, not an array indexed at run time
-            }
+            for (int q = 0; q < 9; ++q) asm volatile("" : "+v"(d[q]));   // nine values, not an array indexed at run time
             // entry (x, y) is d[x][y], or d[y][x] when transposed; on the
             // diagonal the upper triangle serves both halves (bitwise
             // symmetric sums): below the diagonal the mirror is taken when
@@ -330,8 +374,7 @@ __global__ __launch_bounds__(256) void k_elast_pull(const int64_t *__restrict__ 
             acc[5] += up ? d[7] : d[5];
             w0 = w1;
             w1 = w2;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) v[q] = vn[q];
+            v = vn;
         }
     }
 #pragma unroll
@@ -549,7 +592,9 @@ fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args 
     hipError_t e = put(p->mem, &p->e_slot_ptr, sptr, &p->bytes, s);
     if (e == hipSuccess) e = put(p->mem, &p->e_ent, ent, &p->bytes, s);
     if (e == hipSuccess) e = put(p->mem, &p->e_grow, grow, &p->bytes, s);
-    const size_t wbytes = (size_t)C * BLK * (form->prec == FEM_FP64 ? 8 : 4);
+    const size_t wbytes = form->prec == FEM_FP64   ? (size_t)C * NP * Ws<double>::BS * 8
+                          : form->prec == FEM_BF16 ? (size_t)C * NP * Ws<uint16_t>::BS * 2
+                                                   : (size_t)C * NP * Ws<float>::BS * 4;
     if (e == hipSuccess) e = mem_alloc(p->mem, s, false, wbytes ? wbytes : 8, &p->e_work);
     if (e == hipSuccess) p->bytes += wbytes;
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -605,6 +650,10 @@ fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *fo
     if (form->prec == FEM_FP64)
         hipLaunchKernelGGL(k_elast_pull<double>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr, plan->e_ent,
                            plan->e_grow, (const double *)plan->e_work, A->values, ns, (int)(acc == FEM_INC));
+    else if (form->prec == FEM_BF16)
+        hipLaunchKernelGGL(k_elast_pull<uint16_t>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr,
+                           plan->e_ent, plan->e_grow, (const uint16_t *)plan->e_work, A->values, ns,
+                           (int)(acc == FEM_INC));
     else
         hipLaunchKernelGGL(k_elast_pull<float>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr, plan->e_ent,
                            plan->e_grow, (const float *)plan->e_work, A->values, ns, (int)(acc == FEM_INC));
