@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "fem_internal.h"
@@ -464,6 +466,206 @@ fem_status fem_build_sparsity_noalloc(fem_ctx *ctx, const fem_map *rmap, const f
     return sparsity_passes(ctx, rmap, cmap, sp, SparsityScratch(ctx->scratch, ncells, rmap->arity, nrows));
 }
 
+namespace {
+
+// Host inputs of a Mat plan's stream construction, shared read-only by the
+// builder threads.
+struct StreamIn {
+    const int64_t *hrp;     // [nrows+1] CSR row pointers
+    const int32_t *hci;     // CSR column indices
+    const int64_t *hptr;    // [nrows+1] row -> incidence entries
+    const int32_t *hent;    // incidence entries cell*nl + local index, ascending cell
+    const int32_t *hcn;     // cell-to-node Map
+    int nl, MW, NW, SCAP, CCH, NE, ZIDX;
+    int64_t nrows;
+};
+
+// One block's streams: per (chunk, wave) the first batch (relative to the
+// block's own stream), then the batches.
+struct StreamOut {
+    std::vector<int32_t> wq;
+    std::vector<uint16_t> stream;
+    int nq = 0;
+    bool missing = false;
+};
+
+// Scratch of one builder thread (reused over its blocks).
+struct StreamScratch {
+    std::vector<int32_t> colmark;   // [nrows], -1 outside the current row
+    std::vector<int32_t> slot_ptr, lane_ptr, lane_slots, cursor;
+    std::vector<uint16_t> con_idx, con_q;   // per contribution: LDS index of the entry, chunk
+    std::vector<int32_t> weight, home, order, tmp_order, bucket, qstart, lane_of, load;
+    std::vector<std::vector<int32_t>> by_load;
+    std::vector<std::vector<uint16_t>> lane_ent;
+};
+
+// Builds the Mat streams of the block of rows [r0, r1) whose cells are
+// cells[0, nc) (ascending): every Mat value of the block collects its
+// contributions (cell, li, lj) in ascending cell id, values are dealt to
+// lanes by weight (one open per chunk touched plus the entries), and each
+// lane's stream lists, per chunk, "open value" then the value's entries of
+// that chunk.  Depends only on the block, so blocks are built in parallel.
+void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, const int32_t *cells, int64_t nc, StreamScratch &w,
+                 StreamOut &o)
+{
+    const int nl = in.nl, MW = in.MW, NW = in.NW, SCAP = in.SCAP, CCH = in.CCH, NE = in.NE;
+    auto upper = [nl](int i, int j) { if (i > j) std::swap(i, j); return i * (2 * nl - i + 1) / 2 + (j - i); };
+    auto lpos = [cells, nc](int32_t c) { return (int32_t)(std::lower_bound(cells, cells + nc, c) - cells); };
+    if ((int64_t)w.colmark.size() != in.nrows) w.colmark.assign(in.nrows, -1);
+    if ((int)w.lane_ent.size() != MW) w.lane_ent.resize(MW);
+    std::vector<int32_t> &colmark = w.colmark, &slot_ptr = w.slot_ptr, &cursor = w.cursor;
+    std::vector<uint16_t> &con_idx = w.con_idx, &con_q = w.con_q;
+    const int64_t sbase = in.hrp[r0];
+    const int ns = (int)(in.hrp[r1] - sbase);
+    const int nq = (int)((nc + CCH - 1) / CCH);
+    o.nq = nq;
+    slot_ptr.assign(ns + 1, 0);
+    // contributions, grouped by value, ascending cell within a value
+    for (int64_t r = r0; r < r1; ++r) {
+        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = (int32_t)(k - sbase);
+        for (int64_t k = in.hptr[r]; k < in.hptr[r + 1]; ++k) {
+            const int32_t c = in.hent[k] / nl;
+            for (int lj = 0; lj < nl; ++lj) {
+                const int32_t sl = colmark[in.hcn[(int64_t)c * nl + lj]];
+                if (sl < 0) { o.missing = true; continue; }
+                ++slot_ptr[sl + 1];
+            }
+        }
+        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = -1;
+    }
+    for (int t = 0; t < ns; ++t) slot_ptr[t + 1] += slot_ptr[t];
+    con_idx.resize(slot_ptr[ns]);
+    con_q.resize(slot_ptr[ns]);
+    cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
+    for (int64_t r = r0; r < r1; ++r) {
+        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = (int32_t)(k - sbase);
+        for (int64_t k = in.hptr[r]; k < in.hptr[r + 1]; ++k) {
+            const int32_t e = in.hent[k], c = e / nl, li = e % nl, lc = lpos(c);
+            for (int lj = 0; lj < nl; ++lj) {
+                const int32_t sl = colmark[in.hcn[(int64_t)c * nl + lj]];
+                if (sl < 0) continue;
+                const int32_t at = cursor[sl]++;
+                con_idx[at] = (uint16_t)(SCAP + (lc % CCH) * NE + upper(li, lj));
+                con_q[at] = (uint16_t)(lc / CCH);
+            }
+        }
+        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = -1;
+    }
+    // Each value's stream entries per chunk it touches are one open plus
+    // its entries there; its home is the chunk where it has the most.
+    // A (chunk, wave) stream is as long as its longest lane, so the loads
+    // are balanced chunk by chunk: the values homed in chunk q, heaviest
+    // first, go to the lane with the least load in chunk q so far
+    // (longest-processing-time; the load already includes what values
+    // homed in earlier chunks put there).  Loads only grow, so a bucket
+    // queue keyed by load finds that lane; lanes enter in wave-interleaved
+    // order so ties spread over the waves.  With one chunk this is plain
+    // LPT on the value weights.
+    std::vector<int32_t> &home = w.home, &weight = w.weight, &bucket = w.bucket, &tmp_order = w.tmp_order;
+    std::vector<int32_t> &qstart = w.qstart, &order = w.order, &lane_of = w.lane_of, &load = w.load;
+    std::vector<std::vector<int32_t>> &by_load = w.by_load;
+    home.resize(ns);
+    weight.resize(ns);
+    int wmax = 0;
+    for (int t = 0; t < ns; ++t) {
+        int best = 0, hq = 0;
+        for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
+            int32_t k1 = k;
+            while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
+            if (k1 - k + 1 > best) { best = k1 - k + 1; hq = con_q[k]; }
+            k = k1;
+        }
+        home[t] = hq;
+        weight[t] = best;
+        wmax = std::max(wmax, best);
+    }
+    // order: by home chunk, then heaviest first (two stable counting sorts)
+    bucket.assign(wmax + 2, 0);
+    for (int t = 0; t < ns; ++t) ++bucket[wmax - weight[t] + 1];
+    for (int v = 0; v <= wmax; ++v) bucket[v + 1] += bucket[v];
+    tmp_order.resize(ns);
+    for (int t = 0; t < ns; ++t) tmp_order[bucket[wmax - weight[t]]++] = t;
+    qstart.assign(nq + 1, 0);
+    for (int t = 0; t < ns; ++t) ++qstart[home[t] + 1];
+    for (int q = 0; q < nq; ++q) qstart[q + 1] += qstart[q];
+    order.resize(ns);
+    {
+        std::vector<int32_t> fill(qstart.begin(), qstart.end() - 1);
+        for (int p = 0; p < ns; ++p) order[fill[home[tmp_order[p]]]++] = tmp_order[p];
+    }
+    lane_of.resize(ns);
+    load.assign((size_t)nq * MW, 0);
+    for (int q = 0; q < nq; ++q) {
+        if (qstart[q] == qstart[q + 1]) continue;
+        int32_t *lq = load.data() + (size_t)q * MW;
+        int kmax = 0;
+        for (int l = 0; l < MW; ++l) kmax = std::max(kmax, lq[l]);
+        for (auto &v : by_load) v.clear();
+        if ((int)by_load.size() <= kmax) by_load.resize(kmax + 1);
+        for (int i = MW - 1; i >= 0; --i) {
+            const int l = (i % NW) * 64 + i / NW;
+            by_load[lq[l]].push_back(l);
+        }
+        for (int p = qstart[q], m = 0; p < qstart[q + 1]; ++p) {
+            while (by_load[m].empty()) ++m;
+            const int l = by_load[m].back();
+            by_load[m].pop_back();
+            const int t = order[p];
+            lane_of[t] = l;
+            for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
+                int32_t k1 = k;
+                while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
+                load[(size_t)con_q[k] * MW + l] += k1 - k + 1;
+                k = k1;
+            }
+            if ((int)by_load.size() <= lq[l]) by_load.resize(lq[l] + 1);
+            by_load[lq[l]].push_back(l);
+        }
+    }
+    std::vector<int32_t> &lane_ptr = w.lane_ptr, &lane_slots = w.lane_slots;
+    lane_ptr.assign(MW + 1, 0);
+    for (int t = 0; t < ns; ++t) ++lane_ptr[lane_of[t] + 1];
+    for (int l = 0; l < MW; ++l) lane_ptr[l + 1] += lane_ptr[l];
+    lane_slots.resize(ns);
+    {
+        std::vector<int32_t> fill(lane_ptr.begin(), lane_ptr.end() - 1);
+        for (int p = 0; p < ns; ++p) lane_slots[fill[lane_of[order[p]]]++] = order[p];
+    }
+    cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
+    for (int q = 0; q < nq; ++q) {
+        for (int l = 0; l < MW; ++l) {
+            std::vector<uint16_t> &le = w.lane_ent[l];
+            le.clear();
+            for (int32_t k = lane_ptr[l]; k < lane_ptr[l + 1]; ++k) {
+                const int32_t t = lane_slots[k];
+                int32_t &at = cursor[t];
+                if (at == slot_ptr[t + 1] || con_q[at] != q) continue;
+                le.push_back((uint16_t)t);
+                while (at < slot_ptr[t + 1] && con_q[at] == q) le.push_back(con_idx[at++]);
+            }
+        }
+        for (int v = 0; v < NW; ++v) {
+            o.wq.push_back((int32_t)(o.stream.size() / femk::MAT_BATCH));
+            size_t len = 0;
+            for (int l = 64 * v; l < 64 * v + 64; ++l) len = std::max(len, w.lane_ent[l].size());
+            const size_t nb = std::max<size_t>(1, (len + femk::MAT_BATCH - 1) / femk::MAT_BATCH);   // one batch at least
+            for (size_t i = 0; i < nb; ++i)
+                for (int l = 64 * v; l < 64 * v + 64; ++l)
+                    for (size_t j = femk::MAT_BATCH * i; j < femk::MAT_BATCH * (i + 1); ++j)
+                        o.stream.push_back(j < w.lane_ent[l].size() ? w.lane_ent[l][j] : (uint16_t)in.ZIDX);
+        }
+    }
+}
+
+// Threads for the host passes of plan building: the machine's, at most 16.
+int plan_threads()
+{
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, h));
+}
+
+}  // namespace
+
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
                            const fem_sparsity *sp, fem_plan **out)
 {
@@ -542,7 +744,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         rows_cap = std::min<int64_t>(rows_cap, std::max<int64_t>(1, (nrows + want - 1) / want));
     const int lbits = nl <= 4 ? 2 : nl <= 8 ? 3 : nl <= 16 ? 4 : 5;
     std::vector<int32_t> blk_row0{0}, blk_cptr{0}, bcell;
-    std::vector<int32_t> stamp(ncells, -1), lpos(ncells, 0);
+    std::vector<int32_t> stamp(ncells, -1), lpos(is_mat ? 0 : ncells, 0);
     // Dat plans: packed entries
     std::vector<uint16_t> hent16(is_mat ? 0 : hent.size());
     // Mat plans: per-lane LDS index streams (see fem_plan)
@@ -551,176 +753,23 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     const int ZIDX = SCAP + CCH * NE;
     std::vector<int32_t> blk_w{0}, wq;
     std::vector<uint16_t> stream;
-    std::vector<int32_t> colmark(is_mat ? nrows : 0, -1);
-    std::vector<int32_t> slot_ptr, lane_ptr, lane_slots, cursor;
-    std::vector<uint16_t> con_idx, con_q;   // per contribution: LDS index of the entry, chunk
-    std::vector<int32_t> weight, home, order, tmp_order, bucket, qstart, lane_of, load;
-    std::vector<std::vector<int32_t>> by_load;
-    std::vector<std::vector<uint16_t>> lane_ent(MW);
     int64_t nchunks = 0;
     bool missing = false;
-    auto upper = [nl](int i, int j) { if (i > j) std::swap(i, j); return i * (2 * nl - i + 1) / 2 + (j - i); };
     int32_t b = 0;
     int64_t rows = 0, slots = 0, cells = 0;
     size_t first_cell = 0;
     int64_t block_first_row = 0;
-    // Builds the Mat streams of the block [block_first_row, next_row): every
-    // Mat value of the block collects its contributions (cell, li, lj) in
-    // ascending cell id, values are dealt to lanes by weight (one open per
-    // chunk touched plus the entries), and each lane's stream lists, per
-    // chunk, "open value" then the value's entries of that chunk.
-    auto mat_streams = [&](int64_t next_row, int64_t nc) {
-        const int64_t sbase = hrp[block_first_row];
-        const int ns = (int)(hrp[next_row] - sbase);
-        const int nq = (int)((nc + CCH - 1) / CCH);
-        slot_ptr.assign(ns + 1, 0);
-        // contributions, grouped by value, ascending cell within a value
-        for (int64_t r = block_first_row; r < next_row; ++r) {
-            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = (int32_t)(k - sbase);
-            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
-                const int32_t c = hent[k] / nl;
-                for (int lj = 0; lj < nl; ++lj) {
-                    const int32_t sl = colmark[hcn[(int64_t)c * nl + lj]];
-                    if (sl < 0) { missing = true; continue; }
-                    ++slot_ptr[sl + 1];
-                }
-            }
-            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = -1;
-        }
-        for (int t = 0; t < ns; ++t) slot_ptr[t + 1] += slot_ptr[t];
-        con_idx.resize(slot_ptr[ns]);
-        con_q.resize(slot_ptr[ns]);
-        cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
-        for (int64_t r = block_first_row; r < next_row; ++r) {
-            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = (int32_t)(k - sbase);
-            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
-                const int32_t e = hent[k], c = e / nl, li = e % nl, lc = lpos[c];
-                for (int lj = 0; lj < nl; ++lj) {
-                    const int32_t sl = colmark[hcn[(int64_t)c * nl + lj]];
-                    if (sl < 0) continue;
-                    const int32_t at = cursor[sl]++;
-                    con_idx[at] = (uint16_t)(SCAP + (lc % CCH) * NE + upper(li, lj));
-                    con_q[at] = (uint16_t)(lc / CCH);
-                }
-            }
-            for (int64_t k = hrp[r]; k < hrp[r + 1]; ++k) colmark[hci[k]] = -1;
-        }
-        // Each value's stream entries per chunk it touches are one open plus
-        // its entries there; its home is the chunk where it has the most.
-        // A (chunk, wave) stream is as long as its longest lane, so the loads
-        // are balanced chunk by chunk: the values homed in chunk q, heaviest
-        // first, go to the lane with the least load in chunk q so far
-        // (longest-processing-time; the load already includes what values
-        // homed in earlier chunks put there).  Loads only grow, so a bucket
-        // queue keyed by load finds that lane; lanes enter in wave-interleaved
-        // order so ties spread over the waves.  With one chunk this is plain
-        // LPT on the value weights.
-        home.resize(ns);
-        weight.resize(ns);
-        int wmax = 0;
-        for (int t = 0; t < ns; ++t) {
-            int best = 0, hq = 0;
-            for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
-                int32_t k1 = k;
-                while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
-                if (k1 - k + 1 > best) { best = k1 - k + 1; hq = con_q[k]; }
-                k = k1;
-            }
-            home[t] = hq;
-            weight[t] = best;
-            wmax = std::max(wmax, best);
-        }
-        // order: by home chunk, then heaviest first (two stable counting sorts)
-        bucket.assign(wmax + 2, 0);
-        for (int t = 0; t < ns; ++t) ++bucket[wmax - weight[t] + 1];
-        for (int w = 0; w <= wmax; ++w) bucket[w + 1] += bucket[w];
-        tmp_order.resize(ns);
-        for (int t = 0; t < ns; ++t) tmp_order[bucket[wmax - weight[t]]++] = t;
-        qstart.assign(nq + 1, 0);
-        for (int t = 0; t < ns; ++t) ++qstart[home[t] + 1];
-        for (int q = 0; q < nq; ++q) qstart[q + 1] += qstart[q];
-        order.resize(ns);
-        {
-            std::vector<int32_t> fill(qstart.begin(), qstart.end() - 1);
-            for (int p = 0; p < ns; ++p) order[fill[home[tmp_order[p]]]++] = tmp_order[p];
-        }
-        lane_of.resize(ns);
-        load.assign((size_t)nq * MW, 0);
-        for (int q = 0; q < nq; ++q) {
-            if (qstart[q] == qstart[q + 1]) continue;
-            int32_t *lq = load.data() + (size_t)q * MW;
-            int kmax = 0;
-            for (int l = 0; l < MW; ++l) kmax = std::max(kmax, lq[l]);
-            for (auto &v : by_load) v.clear();
-            if ((int)by_load.size() <= kmax) by_load.resize(kmax + 1);
-            for (int i = MW - 1; i >= 0; --i) {
-                const int l = (i % NW) * 64 + i / NW;
-                by_load[lq[l]].push_back(l);
-            }
-            for (int p = qstart[q], m = 0; p < qstart[q + 1]; ++p) {
-                while (by_load[m].empty()) ++m;
-                const int l = by_load[m].back();
-                by_load[m].pop_back();
-                const int t = order[p];
-                lane_of[t] = l;
-                for (int32_t k = slot_ptr[t]; k < slot_ptr[t + 1];) {
-                    int32_t k1 = k;
-                    while (k1 < slot_ptr[t + 1] && con_q[k1] == con_q[k]) ++k1;
-                    load[(size_t)con_q[k] * MW + l] += k1 - k + 1;
-                    k = k1;
-                }
-                if ((int)by_load.size() <= lq[l]) by_load.resize(lq[l] + 1);
-                by_load[lq[l]].push_back(l);
-            }
-        }
-        lane_ptr.assign(MW + 1, 0);
-        for (int t = 0; t < ns; ++t) ++lane_ptr[lane_of[t] + 1];
-        for (int l = 0; l < MW; ++l) lane_ptr[l + 1] += lane_ptr[l];
-        lane_slots.resize(ns);
-        {
-            std::vector<int32_t> fill(lane_ptr.begin(), lane_ptr.end() - 1);
-            for (int p = 0; p < ns; ++p) lane_slots[fill[lane_of[order[p]]]++] = order[p];
-        }
-        cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
-        for (int q = 0; q < nq; ++q) {
-            for (int l = 0; l < MW; ++l) {
-                std::vector<uint16_t> &le = lane_ent[l];
-                le.clear();
-                for (int32_t k = lane_ptr[l]; k < lane_ptr[l + 1]; ++k) {
-                    const int32_t t = lane_slots[k];
-                    int32_t &at = cursor[t];
-                    if (at == slot_ptr[t + 1] || con_q[at] != q) continue;
-                    le.push_back((uint16_t)t);
-                    while (at < slot_ptr[t + 1] && con_q[at] == q) le.push_back(con_idx[at++]);
-                }
-            }
-            for (int w = 0; w < NW; ++w) {
-                wq.push_back((int32_t)(stream.size() / femk::MAT_BATCH));
-                size_t len = 0;
-                for (int l = 64 * w; l < 64 * w + 64; ++l) len = std::max(len, lane_ent[l].size());
-                const size_t nb = std::max<size_t>(1, (len + femk::MAT_BATCH - 1) / femk::MAT_BATCH);   // one batch at least
-                for (size_t i = 0; i < nb; ++i)
-                    for (int l = 64 * w; l < 64 * w + 64; ++l)
-                        for (size_t j = femk::MAT_BATCH * i; j < femk::MAT_BATCH * (i + 1); ++j)
-                            stream.push_back(j < lane_ent[l].size() ? lane_ent[l][j] : (uint16_t)ZIDX);
-            }
-        }
-        nchunks += nq;
-        blk_w.push_back((int32_t)wq.size());
-    };
     auto close_block = [&](int64_t next_row) {
         std::sort(bcell.begin() + first_cell, bcell.end());
-        const int64_t nc = (int64_t)(bcell.size() - first_cell);
-        for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
         if (!is_mat) {
+            for (size_t i = first_cell; i < bcell.size(); ++i) lpos[bcell[i]] = (int32_t)(i - first_cell);
             for (int64_t r = block_first_row; r < next_row; ++r)
                 for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
                     const int32_t e = hent[k];
                     hent16[k] = (uint16_t)((lpos[e / nl] << lbits) | (e % nl));
                 }
-        } else {
-            mat_streams(next_row, nc);
         }
+        // (Mat plans: the block's streams are built once the partition is done)
         blk_row0.push_back((int32_t)next_row);
         blk_cptr.push_back((int32_t)bcell.size());
         first_cell = bcell.size();
@@ -753,6 +802,42 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         cells += fresh;
     }
     if (rows > 0) close_block(nrows);
+    if (is_mat && b > 0) {
+        // the blocks' streams, built on several threads (each block depends
+        // only on its rows and cells), then joined in block order
+        StreamIn in;
+        in.hrp = hrp.data(); in.hci = hci.data(); in.hptr = hptr.data(); in.hent = hent.data();
+        in.hcn = hcn.data();
+        in.nl = nl; in.MW = MW; in.NW = NW; in.SCAP = SCAP; in.CCH = CCH; in.NE = NE; in.ZIDX = ZIDX;
+        in.nrows = nrows;
+        std::vector<StreamOut> outs((size_t)b);
+        std::atomic<int32_t> next{0};
+        auto work = [&]() {
+            StreamScratch w;
+            for (int32_t i; (i = next.fetch_add(1)) < b;)
+                mat_streams(in, blk_row0[i], blk_row0[i + 1], bcell.data() + blk_cptr[i],
+                            blk_cptr[i + 1] - blk_cptr[i], w, outs[i]);
+        };
+        const int nt = std::min<int>(plan_threads(), b);
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (std::thread &t : pool) t.join();
+        size_t total = 0;
+        for (const StreamOut &o : outs) total += o.stream.size();
+        stream.reserve(total);
+        for (StreamOut &o : outs) {
+            missing = missing || o.missing;
+            const int32_t base = (int32_t)(stream.size() / femk::MAT_BATCH);
+            if (stream.size() / femk::MAT_BATCH + o.stream.size() / femk::MAT_BATCH > (size_t)INT32_MAX)
+                return fail(ctx, FEM_E_OVERFLOW, "plan_create: Mat streams exceed 2^31 batches");
+            for (int32_t v : o.wq) wq.push_back(base + v);
+            stream.insert(stream.end(), o.stream.begin(), o.stream.end());
+            nchunks += o.nq;
+            blk_w.push_back((int32_t)wq.size());
+            std::vector<uint16_t>().swap(o.stream);
+        }
+    }
     if (missing) return fail(ctx, FEM_E_ARG, "plan_create: the sparsity lacks entries the Maps reach");
     if (is_mat) {
         wq.push_back((int32_t)(stream.size() / femk::MAT_BATCH));
