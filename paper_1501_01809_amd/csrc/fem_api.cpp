@@ -255,16 +255,38 @@ void sfc_order(const std::vector<double> &pos, int dim, int64_t n, int32_t *perm
     const int bits = dim == 3 ? 21 : 31;
     const double top = (double)((1u << bits) - 1);
     std::vector<std::pair<uint64_t, int32_t>> key(n);
-    for (int64_t i = 0; i < n; ++i) {
-        uint32_t X[3] = {0, 0, 0};
-        for (int r = 0; r < dim; ++r) {
-            const double span = hi[r] > lo[r] ? hi[r] - lo[r] : 1.0;
-            double u = (pos[i * dim + r] - lo[r]) / span * top;
-            X[r] = (uint32_t)std::min(std::max(u, 0.0), top);
+    femk::par_ranges(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            uint32_t X[3] = {0, 0, 0};
+            for (int r = 0; r < dim; ++r) {
+                const double span = hi[r] > lo[r] ? hi[r] - lo[r] : 1.0;
+                double u = (pos[i * dim + r] - lo[r]) / span * top;
+                X[r] = (uint32_t)std::min(std::max(u, 0.0), top);
+            }
+            key[i] = {hilbert_index(X, dim, bits), (int32_t)i};
         }
-        key[i] = {hilbert_index(X, dim, bits), (int32_t)i};
+    });
+    // keys are unique (the index breaks ties), so sorting ranges on their own
+    // threads and merging them gives the one sorted order
+    std::vector<int64_t> cut;
+    femk::par_ranges(n, [&](int64_t i0, int64_t i1) { std::sort(key.begin() + i0, key.begin() + i1); });
+    {
+        const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(femk::host_threads(), n / 65536));
+        for (int t = 0; t <= nt; ++t) cut.push_back(n * t / nt);
     }
-    std::sort(key.begin(), key.end());
+    while (cut.size() > 2) {
+        std::vector<int64_t> next{cut[0]};
+        std::vector<std::thread> pool;
+        for (size_t j = 0; j + 2 < cut.size(); j += 2) {
+            pool.emplace_back([&key, a = cut[j], m = cut[j + 1], e = cut[j + 2]]() {
+                std::inplace_merge(key.begin() + a, key.begin() + m, key.begin() + e);
+            });
+            next.push_back(cut[j + 2]);
+        }
+        if (cut.size() % 2 == 0) next.push_back(cut.back());   // an odd range left over
+        for (std::thread &t : pool) t.join();
+        cut.swap(next);
+    }
     for (int64_t i = 0; i < n; ++i) perm[i] = key[i].second;
 }
 
@@ -657,13 +679,6 @@ void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, const int32_t *cell
     }
 }
 
-// Threads for the host passes of plan building: the machine's, at most 16.
-int plan_threads()
-{
-    const unsigned h = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(16u, h));
-}
-
 }  // namespace
 
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
@@ -818,7 +833,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
                 mat_streams(in, blk_row0[i], blk_row0[i + 1], bcell.data() + blk_cptr[i],
                             blk_cptr[i + 1] - blk_cptr[i], w, outs[i]);
         };
-        const int nt = std::min<int>(plan_threads(), b);
+        const int nt = std::min<int>(femk::host_threads(), b);
         std::vector<std::thread> pool;
         for (int t = 1; t < nt; ++t) pool.emplace_back(work);
         work();

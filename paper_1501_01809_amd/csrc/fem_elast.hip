@@ -33,6 +33,7 @@
 #include "fem_elast_tables.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -521,37 +522,40 @@ fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args 
     const int64_t ns = rpn[N];
     if (ns > INT32_MAX - 1) return efail(ctx, FEM_E_OVERFLOW, "elasticity plan: too many node pairs");
     std::vector<int32_t> cin((size_t)ns);
-    for (int64_t n = 0; n < N; ++n) {
-        const int64_t len = rpn[n + 1] - rpn[n];
-        for (int64_t k = 0; k < len; ++k) {
-            const int32_t c0 = ci3[rp3[3 * n] + 3 * k];
-            if (c0 % 3 || c0 < 0 || c0 >= R || (k > 0 && c0 / 3 <= cin[rpn[n] + k - 1]))
-                return efail(ctx, FEM_E_ARG, "elasticity plan: the CSR is not a 3x3-block expansion of a node pattern");
-            cin[rpn[n] + k] = c0 / 3;
-            for (int x = 0; x < 3; ++x)
-                for (int y = 0; y < 3; ++y)
-                    if (ci3[rp3[3 * n + x] + 3 * k + y] != c0 + y)
-                        return efail(ctx, FEM_E_ARG, "elasticity plan: the CSR is not a 3x3-block expansion of a node pattern");
+    std::atomic<bool> bad{false};
+    par_ranges(N, [&](int64_t n0, int64_t n1) {
+        for (int64_t n = n0; n < n1 && !bad.load(std::memory_order_relaxed); ++n) {
+            const int64_t len = rpn[n + 1] - rpn[n];
+            for (int64_t k = 0; k < len; ++k) {
+                const int32_t c0 = ci3[rp3[3 * n] + 3 * k];
+                bool ok = c0 % 3 == 0 && c0 >= 0 && c0 < R && (k == 0 || c0 / 3 > cin[rpn[n] + k - 1]);
+                for (int x = 0; x < 3 && ok; ++x)
+                    for (int y = 0; y < 3; ++y) ok = ok && ci3[rp3[3 * n + x] + 3 * k + y] == c0 + y;
+                if (!ok) { bad = true; return; }
+                cin[rpn[n] + k] = c0 / 3;
+            }
         }
-    }
+    });
+    if (bad) return efail(ctx, FEM_E_ARG, "elasticity plan: the CSR is not a 3x3-block expansion of a node pattern");
     std::vector<int32_t>().swap(ci3);
     // contributions: slot of every (cell, li, lj), counted then filled in cell order
     std::vector<int32_t> slot_of((size_t)C * NL * NL);
-    std::vector<int32_t> sptr(ns + 1, 0);
-    for (int64_t c = 0; c < C; ++c)
-        for (int li = 0; li < NL; ++li) {
-            const int32_t n = cn[c * NL + li];
-            const int32_t *b0 = cin.data() + rpn[n], *b1 = cin.data() + rpn[n + 1];
-            for (int lj = 0; lj < NL; ++lj) {
-                const int32_t m = cn[c * NL + lj];
-                const int32_t *f = std::lower_bound(b0, b1, m);
-                if (f == b1 || *f != m)
-                    return efail(ctx, FEM_E_ARG, "elasticity plan: the sparsity lacks entries the Maps reach");
-                const int32_t e = (int32_t)(f - cin.data());
-                slot_of[(c * NL + li) * NL + lj] = e;
-                sptr[e + 1]++;
+    par_ranges(C, [&](int64_t ca, int64_t cb) {
+        for (int64_t c = ca; c < cb && !bad.load(std::memory_order_relaxed); ++c)
+            for (int li = 0; li < NL; ++li) {
+                const int32_t n = cn[c * NL + li];
+                const int32_t *b0 = cin.data() + rpn[n], *b1 = cin.data() + rpn[n + 1];
+                for (int lj = 0; lj < NL; ++lj) {
+                    const int32_t m = cn[c * NL + lj];
+                    const int32_t *f = std::lower_bound(b0, b1, m);
+                    if (f == b1 || *f != m) { bad = true; return; }
+                    slot_of[(c * NL + li) * NL + lj] = (int32_t)(f - cin.data());
+                }
             }
-        }
+    });
+    if (bad) return efail(ctx, FEM_E_ARG, "elasticity plan: the sparsity lacks entries the Maps reach");
+    std::vector<int32_t> sptr(ns + 1, 0);
+    for (int32_t e : slot_of) sptr[e + 1]++;
     for (int64_t e = 0; e < ns; ++e) sptr[e + 1] += sptr[e];
     std::vector<uint32_t> ent((size_t)C * NL * NL);
     {

@@ -2,8 +2,11 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "fem.h"
 
@@ -200,6 +203,26 @@ struct Limits {
     int lanes;              // Mat: lanes of the workgroup (the streams are dealt to them)
 };
 bool limits(int dim, int degree, bool is_mat, Limits *out);
+
+// Host threads for the setup passes (plans, renumbering): the machine's, at
+// most 16.
+inline int host_threads()
+{
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, h));
+}
+
+// Runs fn(lo, hi) over [0, n) split into contiguous ranges, one per host
+// thread (one range when n is small).
+template <typename F>
+void par_ranges(int64_t n, F fn)
+{
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / 65536));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+    fn((int64_t)0, n / nt);
+    for (std::thread &t : pool) t.join();
+}
 
 
 }  // namespace femk

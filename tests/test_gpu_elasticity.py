@@ -226,6 +226,17 @@ def test_rejections():
     with pytest.raises(F.FemError) as e:                       # the node CSR is not the vector CSR
         F.fem_plan_create(run.ctx, F.form("elasticity", 3, 2, 3), run.args, run.nsp)
     assert e.value.status == F.FEM_E_ARG
+    R = 3 * p["N"]
+    ci = run.sp.col_idx.clone()
+    ci[1] = ci[0]                                              # right shape, not a 3x3-block expansion
+    with pytest.raises(F.FemError) as e:
+        F.fem_plan_create(run.ctx, F.form("elasticity", 3, 2, 3), run.args, F.Sparsity(run.sp.row_ptr, ci, R, R))
+    assert e.value.status == F.FEM_E_ARG
+    half = run.cn[: run.cn.shape[0] // 2].contiguous()          # a vector CSR of half the cells
+    hsp = F.fem_expand_sparsity(run.ctx, F.fem_build_sparsity(run.ctx, half, p["N"]), 3)
+    with pytest.raises(F.FemError) as e:                       # the sparsity lacks entries the Maps reach
+        F.fem_plan_create(run.ctx, F.form("elasticity", 3, 2, 3), run.args, hsp)
+    assert e.value.status == F.FEM_E_ARG
     no_cc = F.Args(run.cv, run.X, run.cn, p["N"], [run.mu, run.lam])
     with pytest.raises(F.FemError) as e:                       # coordinates need their own Map
         F.fem_plan_create(run.ctx, F.form("elasticity", 3, 2, 3), no_cc, run.sp)
