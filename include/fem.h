@@ -245,9 +245,10 @@ fem_status fem_sync(fem_ctx *ctx);
  *      first call: fills the columns.  Does not synchronise.
  * FEM_E_RANGE if a Map entry is out of range, FEM_E_OVERFLOW if nnz or the
  * incidence count does not fit the library's int32 column/entry indices,
- * FEM_E_UNSUPPORTED if the cells around one row reach more than 2048
- * candidate columns (counted with repetition; about 100 cells around a vertex
- * at P3).
+ * FEM_E_UNSUPPORTED if one row has more than 8192 distinct columns (rows
+ * whose cells reach up to 2048 candidate columns, counted with repetition,
+ * are formed in LDS; longer rows go through an LDS hash set of 8192
+ * columns).
  * Scratch device memory: work_bytes == NULL: the call takes it from the
  * context's allocator and gives it back before returning.  work_bytes !=
  * NULL and work == NULL: a query; *work_bytes receives the bytes the call

@@ -423,7 +423,7 @@ fem_status sparsity_passes(fem_ctx *ctx, const fem_map *rmap, const fem_map *cma
         HIPC(hipMemcpyAsync(&nnz, sp->row_ptr + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s), "copy");
         HIPC(hipStreamSynchronize(s), "sync");
         if (hflag)
-            return fail(ctx, FEM_E_UNSUPPORTED, "build_sparsity: a row reaches more than 2048 candidate columns");
+            return fail(ctx, FEM_E_UNSUPPORTED, "build_sparsity: a row has more than 8192 distinct columns");
         sp->nrows = nrows;
         sp->ncols = ncols;
         sp->nnz = nnz;

@@ -153,6 +153,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int32_t *__restrict
 }
 
 constexpr int RC_CAP = 2048;   // candidate columns of one row held in LDS
+constexpr int HBITS = 13, HCAP = 1 << HBITS;   // distinct columns of one long row (LDS hash set)
 
 // One 64-lane workgroup per row (grid-stride).  Candidates = columns of every
 // incident cell; a candidate is "first" if no equal value precedes it; the
@@ -169,10 +170,7 @@ __global__ __launch_bounds__(64) void k_row_columns(
     for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
         const int64_t e0 = inc_ptr[r], e1 = inc_ptr[r + 1];
         const int64_t n64 = (e1 - e0) * nloc_c;
-        if (n64 > RC_CAP) {
-            if (t0 == 0) atomicOr(overflow, 1);
-            continue;
-        }
+        if (n64 > RC_CAP) continue;   // a long row: k_row_columns_long
         const int n = (int)n64;
         for (int t = t0; t < n; t += 64) {
             int64_t e = inc_ent[e0 + t / nloc_c];
@@ -204,6 +202,67 @@ __global__ __launch_bounds__(64) void k_row_columns(
             }
         }
         __syncthreads();
+    }
+}
+
+// Rows with more than RC_CAP candidates (high-valence vertices).  64-lane
+// workgroups walk groups of 64 rows: the lanes find the long rows among them,
+// then take each long row together: its candidates go into an LDS hash set
+// (open addressing, at most HCAP distinct columns, else *overflow), and each
+// distinct column's rank among the set is its position in the sorted row.
+// The result does not depend on the insertion order.
+__global__ __launch_bounds__(64) void k_row_columns_long(
+    const int64_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_ent, int nloc_r,
+    const int32_t *__restrict__ cmap, int nloc_c, int64_t nrows, int32_t *__restrict__ counts,
+    const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col_idx, int *__restrict__ overflow)
+{
+    __shared__ int32_t tab[HCAP];
+    __shared__ int32_t nu;
+    const int lane = threadIdx.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < nrows; r0 += (int64_t)gridDim.x * 64) {
+        const int64_t my = r0 + lane;
+        const bool is_long = my < nrows && (inc_ptr[my + 1] - inc_ptr[my]) * nloc_c > RC_CAP;
+        uint64_t pending = __ballot(is_long);
+        while (pending) {
+            const int j = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const int64_t r = r0 + j;
+            for (int i = lane; i < HCAP; i += 64) tab[i] = -1;
+            if (lane == 0) nu = 0;
+            __syncthreads();
+            const int64_t e0 = inc_ptr[r], n = (inc_ptr[r + 1] - e0) * nloc_c;
+            int full = 0;
+            for (int64_t t = lane; t < n && !full; t += 64) {
+                const int64_t e = inc_ent[e0 + t / nloc_c];
+                const int32_t v = cmap[(e / nloc_r) * nloc_c + t % nloc_c];
+                uint32_t h = ((uint32_t)v * 2654435761u) >> (32 - HBITS);   // Knuth's multiplicative hash
+                for (int probe = 0;; ++probe) {
+                    if (probe == HCAP) { full = 1; break; }
+                    const int32_t old = atomicCAS(&tab[h], -1, v);
+                    if (old == -1) { atomicAdd(&nu, 1); break; }
+                    if (old == v) break;
+                    h = (h + 1) & (HCAP - 1);
+                }
+            }
+            __syncthreads();
+            if (__ballot(full) != 0) {   // (one wave: uniform)
+                if (lane == 0) atomicOr(overflow, 1);
+                continue;                // the next long row clears the table first
+            }
+            if (!col_idx) {
+                if (lane == 0) counts[r] = nu;
+            } else {
+                const int64_t base = row_ptr[r];
+                for (int i = lane; i < HCAP; i += 64) {
+                    const int32_t v = tab[i];
+                    if (v < 0) continue;
+                    int rank = 0;
+                    for (int k = 0; k < HCAP; ++k) rank += (uint32_t)tab[k] < (uint32_t)v;
+                    col_idx[base + rank] = v;
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -288,6 +347,9 @@ hipError_t row_columns(const int64_t *inc_ptr, const int32_t *inc_ent, int nloc_
     int64_t g = nrows < 32768 ? nrows : 32768;
     hipLaunchKernelGGL(k_row_columns, dim3((unsigned)g), dim3(64), 0, s, inc_ptr, inc_ent, nloc_r,
                        cmap, nloc_c, nrows, counts, row_ptr, col_idx, overflow);
+    const int64_t gl = std::min<int64_t>((nrows + 63) / 64, 4096);
+    hipLaunchKernelGGL(k_row_columns_long, dim3((unsigned)gl), dim3(64), 0, s, inc_ptr, inc_ent,
+                       nloc_r, cmap, nloc_c, nrows, counts, row_ptr, col_idx, overflow);
     return hipGetLastError();
 }
 

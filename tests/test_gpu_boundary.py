@@ -131,27 +131,36 @@ def test_quadrature_degree():
     assert e.value.status == F.FEM_E_UNSUPPORTED
 
 
-def test_row_candidate_limit_is_a_status():
-    """A vertex with 700 triangles around it: its row gathers 2100 candidate
-    columns (with repetition), beyond the 2048 a row's LDS holds; the count
-    pass reports FEM_E_UNSUPPORTED instead of a wrong pattern."""
+def test_long_rows_and_the_distinct_column_limit():
+    """Fans of m triangles around one vertex: its row gathers 3m candidate
+    columns (with repetition).  Up to 2048 candidates the row is formed in
+    LDS; beyond, through the long-row hash set, up to 8192 distinct columns.
+    Both match the oracle bit for bit (with ordinary rows around them, and
+    several long rows in one 64-row group); a row of 8201 distinct columns
+    makes the count pass report FEM_E_UNSUPPORTED instead of a wrong
+    pattern."""
     import torch
     from paper_1501_01809_amd import fem as F
-    n = 700
-    t = np.arange(n)
-    tri = np.stack([np.zeros(n, dtype=np.int32), 1 + t, 1 + (t + 1) % n], 1).astype(np.int32)
-    cn = torch.from_numpy(tri).cuda()
     ctx = F.Context(0)
+
+    def fans(sizes):
+        tris, off = [], 0
+        for m in sizes:
+            t = np.arange(m)
+            tris.append(np.stack([np.full(m, off), off + 1 + t, off + 1 + (t + 1) % m], 1))
+            off += m + 1
+        return np.concatenate(tris).astype(np.int32), off
+
+    for sizes in ([600], [700], [3000], [700, 3, 2100, 5, 8191], [40] * 10 + [683, 4000]):
+        tri, nv = fans(sizes)
+        sp = F.fem_build_sparsity(ctx, torch.from_numpy(tri).cuda(), nv)
+        rp, ci = oracle.sparsity(tri, nv)
+        assert np.array_equal(sp.row_ptr.cpu().numpy(), rp), sizes
+        assert np.array_equal(sp.col_idx.cpu().numpy(), ci), sizes
+    tri, nv = fans([8200])
     with pytest.raises(F.FemError) as e:
-        F.fem_build_sparsity(ctx, cn, n + 1)
-    assert e.value.status == F.FEM_E_UNSUPPORTED and "2048" in str(e.value)
-    # 600 triangles (1800 candidates) are within the limit and match the oracle
-    m = 600
-    t = np.arange(m)
-    tri = np.stack([np.zeros(m, dtype=np.int32), 1 + t, 1 + (t + 1) % m], 1).astype(np.int32)
-    sp = F.fem_build_sparsity(ctx, torch.from_numpy(tri).cuda(), m + 1)
-    rp, ci = oracle.sparsity(tri, m + 1)
-    assert np.array_equal(sp.row_ptr.cpu().numpy(), rp) and np.array_equal(sp.col_idx.cpu().numpy(), ci)
+        F.fem_build_sparsity(ctx, torch.from_numpy(tri).cuda(), nv)
+    assert e.value.status == F.FEM_E_UNSUPPORTED and "8192" in str(e.value)
 
 
 def test_mat_row_longer_than_the_value_area_is_a_status():
