@@ -521,14 +521,15 @@ struct StreamScratch {
     std::vector<std::vector<uint16_t>> lane_ent;
 };
 
-// Builds the Mat streams of the block of rows [r0, r1) whose cells are
+// Builds the Mat streams of the block of Mat values [v0, v1) in rows
+// [r0, r1) (all of their values, or a slice of one long row) whose cells are
 // cells[0, nc) (ascending): every Mat value of the block collects its
 // contributions (cell, li, lj) in ascending cell id, values are dealt to
 // lanes by weight (one open per chunk touched plus the entries), and each
 // lane's stream lists, per chunk, "open value" then the value's entries of
 // that chunk.  Depends only on the block, so blocks are built in parallel.
-void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, const int32_t *cells, int64_t nc, StreamScratch &w,
-                 StreamOut &o)
+void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, int64_t v0, int64_t v1, const int32_t *cells, int64_t nc,
+                 StreamScratch &w, StreamOut &o)
 {
     const int nl = in.nl, MW = in.MW, NW = in.NW, SCAP = in.SCAP, CCH = in.CCH, NE = in.NE;
     auto upper = [nl](int i, int j) { if (i > j) std::swap(i, j); return i * (2 * nl - i + 1) / 2 + (j - i); };
@@ -537,19 +538,26 @@ void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, const int32_t *cell
     if ((int)w.lane_ent.size() != MW) w.lane_ent.resize(MW);
     std::vector<int32_t> &colmark = w.colmark, &slot_ptr = w.slot_ptr, &cursor = w.cursor;
     std::vector<uint16_t> &con_idx = w.con_idx, &con_q = w.con_q;
-    const int64_t sbase = in.hrp[r0];
-    const int ns = (int)(in.hrp[r1] - sbase);
+    const int64_t sbase = v0;
+    const int ns = (int)(v1 - v0);
+    // a column of the row: its value's slot in the block, -2 outside the
+    // block's slice; -1: not in the row (the sparsity lacks it)
+    auto mark_row = [&](int64_t r) {
+        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k)
+            colmark[in.hci[k]] = k >= v0 && k < v1 ? (int32_t)(k - sbase) : -2;
+    };
     const int nq = (int)((nc + CCH - 1) / CCH);
     o.nq = nq;
     slot_ptr.assign(ns + 1, 0);
     // contributions, grouped by value, ascending cell within a value
     for (int64_t r = r0; r < r1; ++r) {
-        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = (int32_t)(k - sbase);
+        mark_row(r);
         for (int64_t k = in.hptr[r]; k < in.hptr[r + 1]; ++k) {
             const int32_t c = in.hent[k] / nl;
             for (int lj = 0; lj < nl; ++lj) {
                 const int32_t sl = colmark[in.hcn[(int64_t)c * nl + lj]];
-                if (sl < 0) { o.missing = true; continue; }
+                if (sl == -1) o.missing = true;
+                if (sl < 0) continue;
                 ++slot_ptr[sl + 1];
             }
         }
@@ -560,7 +568,7 @@ void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, const int32_t *cell
     con_q.resize(slot_ptr[ns]);
     cursor.assign(slot_ptr.begin(), slot_ptr.end() - 1);
     for (int64_t r = r0; r < r1; ++r) {
-        for (int64_t k = in.hrp[r]; k < in.hrp[r + 1]; ++k) colmark[in.hci[k]] = (int32_t)(k - sbase);
+        mark_row(r);
         for (int64_t k = in.hptr[r]; k < in.hptr[r + 1]; ++k) {
             const int32_t e = in.hent[k], c = e / nl, li = e % nl, lc = lpos(c);
             for (int lj = 0; lj < nl; ++lj) {
@@ -768,6 +776,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
     const int ZIDX = SCAP + CCH * NE;
     std::vector<int32_t> blk_w{0}, wq;
     std::vector<uint16_t> stream;
+    std::vector<int64_t> mb_r0, mb_r1, mb_v0, mb_v1;   // Mat blocks: rows and Mat values
     int64_t nchunks = 0;
     bool missing = false;
     int32_t b = 0;
@@ -785,6 +794,12 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
                 }
         }
         // (Mat plans: the block's streams are built once the partition is done)
+        if (is_mat) {
+            mb_r0.push_back(block_first_row);
+            mb_r1.push_back(next_row);
+            mb_v0.push_back(hrp[block_first_row]);
+            mb_v1.push_back(hrp[next_row]);
+        }
         blk_row0.push_back((int32_t)next_row);
         blk_cptr.push_back((int32_t)bcell.size());
         first_cell = bcell.size();
@@ -802,9 +817,41 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
             fresh = hptr[r + 1] - hptr[r];
         }
         // (a Mat row whose cells exceed one chunk gets a block of several chunks)
-        if ((is_mat && rs > lim.slot_cap) || (!is_mat && fresh > lim.cell_cap))
+        if (!is_mat && fresh > lim.cell_cap)
             return fail(ctx, FEM_E_UNSUPPORTED, "plan_create: row %lld is too long for one workgroup",
                         (long long)r);
+        if (is_mat && rs > lim.slot_cap) {
+            // A Mat row with more values than a block holds: blocks of
+            // consecutive slices of its values, each gathering the row's
+            // cells (the block before it was closed above).
+            for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
+                const int32_t c = hent[k] / nl;
+                if (stamp[c] != b) {
+                    stamp[c] = b;
+                    bcell.push_back(c);
+                }
+            }
+            std::sort(bcell.begin() + first_cell, bcell.end());
+            const size_t rc0 = first_cell, nrc = bcell.size() - first_cell;
+            for (int64_t v0 = hrp[r]; v0 < hrp[r + 1]; v0 += lim.slot_cap) {
+                if (v0 > hrp[r])
+                    for (size_t i = 0; i < nrc; ++i) {
+                        const int32_t c = bcell[rc0 + i];
+                        bcell.push_back(c);
+                    }
+                mb_r0.push_back(r);
+                mb_r1.push_back(r + 1);
+                mb_v0.push_back(v0);
+                mb_v1.push_back(std::min<int64_t>(v0 + lim.slot_cap, hrp[r + 1]));
+                blk_row0.push_back((int32_t)(r + 1));
+                blk_cptr.push_back((int32_t)bcell.size());
+                first_cell = bcell.size();
+                ++b;
+            }
+            block_first_row = r + 1;
+            rows = slots = cells = 0;
+            continue;
+        }
         for (int64_t k = hptr[r]; k < hptr[r + 1]; ++k) {
             const int32_t c = hent[k] / nl;
             if (stamp[c] != b) {
@@ -830,7 +877,7 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         auto work = [&]() {
             StreamScratch w;
             for (int32_t i; (i = next.fetch_add(1)) < b;)
-                mat_streams(in, blk_row0[i], blk_row0[i + 1], bcell.data() + blk_cptr[i],
+                mat_streams(in, mb_r0[i], mb_r1[i], mb_v0[i], mb_v1[i], bcell.data() + blk_cptr[i],
                             blk_cptr[i + 1] - blk_cptr[i], w, outs[i]);
         };
         const int nt = std::min<int>(femk::host_threads(), b);
@@ -902,10 +949,10 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         std::vector<int32_t> hdr((size_t)b * 8, 0);
         for (int32_t i = 0; i < b; ++i) {
             int32_t *hd = &hdr[(size_t)i * 8];
-            const int64_t s0 = hrp[blk_row0[i]];
+            const int64_t s0 = mb_v0[i];
             hd[0] = (int32_t)(uint32_t)(s0 & 0xffffffff);
             hd[1] = (int32_t)(s0 >> 32);
-            hd[2] = (int32_t)(hrp[blk_row0[i + 1]] - s0);
+            hd[2] = (int32_t)(mb_v1[i] - s0);
             hd[3] = blk_cptr[i];
             hd[4] = blk_cptr[i + 1] - blk_cptr[i];
             hd[5] = (blk_w[i + 1] - blk_w[i]) / NW;

@@ -163,12 +163,14 @@ def test_long_rows_and_the_distinct_column_limit():
     assert e.value.status == F.FEM_E_UNSUPPORTED and "8192" in str(e.value)
 
 
-def test_mat_row_longer_than_the_value_area_is_a_status():
+def test_mat_row_longer_than_the_value_area():
     """A caller's CSR may hold more entries than the Maps reach.  A P2
     tetrahedron row whose CSR row is dense (9,261 columns, beyond the 6,392
-    values a block's LDS holds) makes plan creation report FEM_E_UNSUPPORTED;
-    the same sparsity with row 0 cut back to its mesh columns plus a few
-    extra ones builds, and the extra entries assemble to zero."""
+    values a block's LDS holds) is cut into blocks of consecutive slices of
+    its values, each gathering the row's cells; with row 0 dense, and with
+    rows 0 and 7 dense around ordinary rows, the matrix matches the oracle,
+    the entries the Maps do not reach assemble to zero, and INC adds to the
+    values bit for bit as WRITE computes them."""
     import torch
     from paper_1501_01809_amd import fem as F
     c = make_case("cube", 10, 2)
@@ -177,28 +179,30 @@ def test_mat_row_longer_than_the_value_area_is_a_status():
     rp, ci = oracle.sparsity(c.cell_node, N)
     assert N > 6392
 
-    def with_row0(cols0):
-        cols = [np.asarray(cols0, dtype=np.int32)] + [ci[rp[r]:rp[r + 1]] for r in range(1, N)]
+    def with_rows(dense):
+        cols = [np.arange(N, dtype=np.int32) if r in dense else ci[rp[r]:rp[r + 1]] for r in range(N)]
         lens = np.array([len(x) for x in cols], dtype=np.int64)
         row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
-        return F.Sparsity(torch.from_numpy(row_ptr).cuda(), torch.from_numpy(np.concatenate(cols)).cuda(), N, N), \
-            row_ptr, np.concatenate(cols)
+        col = np.concatenate(cols)
+        return F.Sparsity(torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda(), N, N), row_ptr, col
 
-    sp, _, _ = with_row0(np.arange(N))
-    with pytest.raises(F.FemError) as e:
-        F.fem_plan_create(g.ctx, g.form, g.args_k, sp)
-    assert e.value.status == F.FEM_E_UNSUPPORTED and "too long" in str(e.value)
-    extra = np.union1d(ci[rp[0]:rp[1]], np.arange(N - 40, N))
-    sp2, rp2, ci2 = with_row0(extra)
-    plan = F.fem_plan_create(g.ctx, g.form, g.args_k, sp2)
-    vals = torch.zeros(ci2.size, dtype=torch.float64, device="cuda")
-    F.fem_par_loop_assemble_mat(g.ctx, plan, g.form, g.args_k, vals, sp2)
-    F.fem_sync(g.ctx)
-    got = vals.cpu().numpy()
-    v, va = oracle.assemble_mat(c.dim, 2, c.cells, c.coords, c.cell_node, c.kappa, rp2, ci2)
-    check_close(got, v, va, "mat with extra row-0 entries", row_ptr=rp2)
-    mesh_cols = set(ci[rp[0]:rp[1]].tolist())
-    assert all(got[k] == 0.0 for k in range(rp2[0], rp2[1]) if ci2[k] not in mesh_cols)
+    for dense in ({0}, {0, 7}):
+        sp, rp2, ci2 = with_rows(dense)
+        plan = F.fem_plan_create(g.ctx, g.form, g.args_k, sp)
+        vals = torch.zeros(ci2.size, dtype=torch.float64, device="cuda")
+        F.fem_par_loop_assemble_mat(g.ctx, plan, g.form, g.args_k, vals, sp)
+        F.fem_sync(g.ctx)
+        got = vals.cpu().numpy()
+        v, va = oracle.assemble_mat(c.dim, 2, c.cells, c.coords, c.cell_node, c.kappa, rp2, ci2)
+        check_close(got, v, va, f"mat with dense rows {sorted(dense)}", row_ptr=rp2)
+        for r in dense:
+            mesh_cols = set(ci[rp[r]:rp[r + 1]].tolist())
+            assert all(got[k] == 0.0 for k in range(rp2[r], rp2[r + 1]) if ci2[k] not in mesh_cols)
+        base = torch.from_numpy(np.linspace(-1.0, 1.0, ci2.size)).cuda()
+        acc = base.clone()
+        F.fem_par_loop_assemble_mat(g.ctx, plan, g.form, g.args_k, acc, sp, F.FEM_INC)
+        F.fem_sync(g.ctx)
+        assert np.array_equal(acc.cpu().numpy(), (base + vals).cpu().numpy())
 
 
 def test_dat_row_with_more_cells_than_a_block_holds_is_a_status():
