@@ -103,9 +103,10 @@ typedef enum fem_cell { FEM_TRIANGLE = 2, FEM_TETRAHEDRON = 3 } fem_cell;
  * element contraction (the reference tensor and the per-cell geometry
  * factor, scaled per cell by a power of two) are rounded to that type and
  * multiplied on the matrix cores with FP32 accumulation; the element blocks
- * are kept in FP32 (FEM_FP32, FEM_FP16) or bfloat16 (FEM_BF16) until they
- * are summed; the Jacobian, its determinant and inverse are FP64 for every
- * cell, and the global sums are FP64.  Other combinations return
+ * are kept in FP32 (FEM_FP32), bfloat16 (FEM_BF16) or binary16 with a
+ * power-of-two scale per cell (FEM_FP16) until they are summed; the
+ * Jacobian, its determinant and inverse are FP64 for every cell, and the
+ * global sums are FP64.  Other combinations return
  * FEM_E_UNSUPPORTED. */
 typedef enum fem_prec { FEM_FP64 = 0, FEM_FP32 = 1, FEM_BF16 = 2, FEM_FP16 = 3 } fem_prec;
 
@@ -308,8 +309,9 @@ fem_status fem_expand_sparsity(fem_ctx *ctx, const fem_sparsity *node, int32_t b
  * node sparsity, e.g. from fem_expand_sparsity) hold, per node pair, the
  * list of its (cell, local pair) contributions in ascending cell id, and a
  * workspace for the element blocks of every cell ([cells][55][9] values of
- * float64 for FEM_FP64, float32 for FEM_FP32 and FEM_FP16; [cells][55][10]
- * bfloat16, the last of each ten unused, for FEM_BF16).  Assembly calls on one plan
+ * float64 for FEM_FP64, float32 for FEM_FP32; [cells][55][10] 16-bit values
+ * for FEM_BF16, bfloat16 with the tenth unused, and FEM_FP16, binary16 with
+ * the tenth holding the cell's scale exponent).  Assembly calls on one plan
  * share that workspace: they must not overlap in time (queue them on one
  * stream).  FEM_E_OVERFLOW for 2^24 cells or more.
  */

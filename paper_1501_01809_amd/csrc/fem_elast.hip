@@ -19,8 +19,8 @@
 // scaled per cell by a power of two (exact) that brings its entries to
 // magnitude <= 1, and the FP32 accumulator is scaled back; accumulation is in
 // FP32 (FP64 for the FP64 path).  The blocks (i <= j, 3 x 3 each) go to a
-// plan-owned workspace E[cell][pair][a*3+b] (FP64; FP32 for the FP32 and FP16
-// contractions; bfloat16, padded to ten values per block, for BF16).
+// plan-owned workspace E[cell][pair][a*3+b] (FP64; FP32 for the FP32
+// contraction; 16-bit values, ten per block, for BF16 and FP16).
 //
 // Stage 2, k_elast_pull: one lane per node pair (i, j) of the node sparsity,
 // a 3 x 3 block of the vector CSR.  The lane walks the plan's list of
@@ -89,23 +89,40 @@ template <> struct Mf<FEM_FP16> {
     static __device__ __forceinline__ Acc mma(In a, In b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
 };
 
-// Workspace element: FP64 and FP32 blocks of nine values; BF16 contractions
-// store their blocks as bfloat16 bits, nine values and one pad (20-byte,
-// 4-byte aligned blocks: the pull reads one with a 16-byte and a 4-byte
-// load instead of three), which halves the workspace; FP16 keeps FP32 (its
-// outputs are not kept in FP16 range by the operand scaling).
+// Workspace element: FP64 and FP32 blocks of nine values (FP64 for the FP64
+// contraction, FP32 for FP32).  The narrow contractions store 16-bit values,
+// nine and one more per block (20-byte, 4-byte aligned blocks: the pull
+// reads one with a 16-byte and a 4-byte load instead of three), which halves
+// the workspace: BF16 the scaled-back values as bfloat16 bits (the tenth
+// unused); FP16 the accumulator before it is scaled back, which the operand
+// scaling keeps within FP16 range, as binary16 bits, the tenth holding the
+// cell's scale exponent (the scale is a power of two, so the pull restores
+// the value exactly).
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+struct half_ws { uint16_t bits; };   // FP16 workspace element
 template <typename W> struct Ws;
 template <> struct Ws<double> { static constexpr int BS = 9; };
 template <> struct Ws<float> { static constexpr int BS = 9; };
 template <> struct Ws<uint16_t> { static constexpr int BS = 10; };
+template <> struct Ws<half_ws> { static constexpr int BS = 10; };
 template <int P> struct WsOf { typedef float T; };
 template <> struct WsOf<FEM_FP64> { typedef double T; };
 template <> struct WsOf<FEM_BF16> { typedef uint16_t T; };
-__device__ __forceinline__ void ws_put(double *E, double v) { *E = v; }
-__device__ __forceinline__ void ws_put(float *E, float v) { *E = v; }
-__device__ __forceinline__ void ws_put(uint16_t *E, float v) { *E = (uint16_t)f2bf(v); }
+template <> struct WsOf<FEM_FP16> { typedef half_ws T; };
+// Stores entry ab of a block (E the block's first element); acc is the
+// contraction's accumulator, scale = 2^sexp the cell's operand scale.
+__device__ __forceinline__ void ws_put(double *E, int ab, double acc, double scale, int) { E[ab] = acc * scale; }
+__device__ __forceinline__ void ws_put(float *E, int ab, float acc, double scale, int) { E[ab] = acc * (float)scale; }
+__device__ __forceinline__ void ws_put(uint16_t *E, int ab, float acc, double scale, int)
+{
+    E[ab] = (uint16_t)f2bf(acc * (float)scale);
+}
+__device__ __forceinline__ void ws_put(half_ws *E, int ab, float acc, double, int)
+{
+    E[ab].bits = __builtin_bit_cast(uint16_t, (_Float16)acc);   // (the exponent: after the tiles)
+}
 __device__ __forceinline__ double bf2d(uint32_t bits16) { return (double)__uint_as_float(bits16 << 16); }
+__device__ __forceinline__ double h2d(uint32_t bits16) { return (double)(float)__builtin_bit_cast(_Float16, (uint16_t)bits16); }
 // One block as loaded (raw, so that a block loaded ahead is not waited for
 // until it is used), and its nine values as doubles.
 template <typename W> struct Blk {
@@ -136,6 +153,26 @@ template <> struct Blk<uint16_t> {
         d[4] = bf2d(w.z & 0xffffu); d[5] = bf2d(w.z >> 16);
         d[6] = bf2d(w.w & 0xffffu); d[7] = bf2d(w.w >> 16);
         d[8] = bf2d(w4 & 0xffffu);
+    }
+};
+
+template <> struct Blk<half_ws> {
+    u32x4a w;
+    uint32_t w4;
+    __device__ __forceinline__ void load(const half_ws *b)
+    {
+        w = *reinterpret_cast<const u32x4a *>(b);
+        w4 = *reinterpret_cast<const uint32_t *>(b + 8);
+    }
+    __device__ __forceinline__ void get(double (&d)[9]) const
+    {
+        // 2^e, e the cell's scale exponent (the block's tenth element)
+        const double sc = ldexp(1.0, (int)(int16_t)(w4 >> 16));
+        d[0] = h2d(w.x & 0xffffu) * sc; d[1] = h2d(w.x >> 16) * sc;
+        d[2] = h2d(w.y & 0xffffu) * sc; d[3] = h2d(w.y >> 16) * sc;
+        d[4] = h2d(w.z & 0xffffu) * sc; d[5] = h2d(w.z >> 16) * sc;
+        d[6] = h2d(w.w & 0xffffu) * sc; d[7] = h2d(w.w >> 16) * sc;
+        d[8] = h2d(w4 & 0xffffu) * sc;
     }
 };
 
@@ -307,8 +344,18 @@ __global__ __launch_bounds__(EWG) void k_elast_element(ElArgs a)
                 for (int v = 0; v < 4; ++v) {
                     const int pr = 16 * mt + M::row(lane, v);
                     if (live && pr < NP)
-                        ws_put(E + cell * (NP * BS) + pr * BS + ab, acc[v] * (typename M::Out)scale);
+                        ws_put(E + cell * (NP * BS) + pr * BS, ab, acc[v], scale, 0);
                 }
+            }
+        }
+        if constexpr (P == FEM_FP16) {
+            // the tenth element of every block: the cell's scale exponent
+            for (int i = lane; i < CPW * NP; i += 64) {
+                const int cq = i / NP, pr = i - cq * NP;
+                const int64_t cell = g * CPW + cq;
+                if (g < ngroups && cell < a.ncells)
+                    reinterpret_cast<half_ws *>(E)[cell * (NP * BS) + pr * BS + 9].bits =
+                        (uint16_t)(int16_t)ilogb(geo[wv][cq][G_SCALE]);
             }
         }
         __syncthreads();
@@ -598,6 +645,7 @@ fem_status elast_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args 
     if (e == hipSuccess) e = put(p->mem, &p->e_grow, grow, &p->bytes, s);
     const size_t wbytes = form->prec == FEM_FP64   ? (size_t)C * NP * Ws<double>::BS * 8
                           : form->prec == FEM_BF16 ? (size_t)C * NP * Ws<uint16_t>::BS * 2
+                          : form->prec == FEM_FP16 ? (size_t)C * NP * Ws<half_ws>::BS * 2
                                                    : (size_t)C * NP * Ws<float>::BS * 4;
     if (e == hipSuccess) e = mem_alloc(p->mem, s, false, wbytes ? wbytes : 8, &p->e_work);
     if (e == hipSuccess) p->bytes += wbytes;
@@ -657,6 +705,10 @@ fem_status elast_assemble(fem_ctx *ctx, const fem_plan *plan, const fem_form *fo
     else if (form->prec == FEM_BF16)
         hipLaunchKernelGGL(k_elast_pull<uint16_t>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr,
                            plan->e_ent, plan->e_grow, (const uint16_t *)plan->e_work, A->values, ns,
+                           (int)(acc == FEM_INC));
+    else if (form->prec == FEM_FP16)
+        hipLaunchKernelGGL(k_elast_pull<half_ws>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr,
+                           plan->e_ent, plan->e_grow, (const half_ws *)plan->e_work, A->values, ns,
                            (int)(acc == FEM_INC));
     else
         hipLaunchKernelGGL(k_elast_pull<float>, dim3(pg), dim3(256), 0, s, plan->row_ptr, plan->e_slot_ptr, plan->e_ent,

@@ -71,8 +71,8 @@ struct fem_plan {
     // Elasticity plans (is_mat == 2): per node pair of the node sparsity (a
     // 3x3 block of the vector CSR), its contributions in ascending cell id,
     // and the element-block workspace [ncells][55][9] (float64 for FEM_FP64,
-    // float32 for FEM_FP32 and FEM_FP16; [ncells][55][10] bfloat16 for
-    // FEM_BF16).
+    // float32 for FEM_FP32; [ncells][55][10] 16-bit values for FEM_BF16 and
+    // FEM_FP16).
     int32_t *e_slot_ptr = nullptr;  // [nslots+1]
     uint32_t *e_ent = nullptr;      // (cell << 8) | (pair << 2) | (diagonal << 1) | transposed
     int32_t *e_grow = nullptr;      // [nslots/64 + 1] node row of slot 64 g

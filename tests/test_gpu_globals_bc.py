@@ -5,7 +5,7 @@ import pytest
 
 import fem_inputs as fi
 import oracle
-from fem_case import make_case
+from fem_case import check_close, make_case
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +103,18 @@ def test_dirichlet_matches_oracle_and_patch_test(kind, n, degree):
     rv, rb, rab = oracle.apply_dirichlet(rp, ci, v0, b0, mask, gvals, 1.0)
     assert np.array_equal(vb.cpu().numpy(), rv)
     assert np.all(np.abs(bb.cpu().numpy() - rb) <= 1e-12 * rab + 1e-300)
+    # end to end: oracle assembly then oracle conditions, against the GPU's
+    # assembly then the GPU's conditions (the matrix within the assembly bar;
+    # the lifted right-hand side within the bar carried through the lifting)
+    ov, oa = oracle.assemble_mat(case.dim, degree, case.cells, case.coords, case.cell_node,
+                                 np.ones(case.coords.shape[0]), rp, ci, form="laplace")
+    ev, eb, eab = oracle.apply_dirichlet(rp, ci, ov, b0, mask, gvals, 1.0)
+    oa_bc = np.where(ev == ov, oa, 0.0)                   # kept entries keep their scale; set ones are exact
+    check_close(vb.cpu().numpy(), ev, oa_bc, "assembly + Dirichlet, end to end", row_ptr=rp)
+    lift = np.zeros(case.nnodes)                          # sum over kept columns of |a_rj g_j| per row
+    rows = np.repeat(np.arange(case.nnodes), np.diff(rp))
+    np.add.at(lift, rows, np.where(mask[ci] == 1, oa * np.abs(gvals[ci]), 0.0))
+    assert np.all(np.abs(bb.cpu().numpy() - eb) <= 1e-12 * (eab + lift) + 1e-300)
     A = np.zeros((case.nnodes, case.nnodes))
     for r in range(case.nnodes):
         A[r, ci[rp[r]:rp[r + 1]]] = rv[rp[r]:rp[r + 1]]
