@@ -186,11 +186,19 @@ template <> __device__ __forceinline__ v4s pack<FEM_BF16>(const double *g)
     r[0] = f2bf((float)g[0]); r[1] = f2bf((float)g[1]); r[2] = f2bf((float)g[2]); r[3] = f2bf((float)g[3]);
     return r;
 }
+// double -> float -> binary16, both roundings to nearest even on the
+// hardware converters (left to itself the compiler folds the two into one
+// double -> half conversion, which it expands into a long integer sequence)
+__device__ __forceinline__ _Float16 d2h(double g)
+{
+    float f = (float)g;
+    asm volatile("" : "+v"(f));
+    return (_Float16)f;
+}
 template <> __device__ __forceinline__ v4h pack<FEM_FP16>(const double *g)
 {
     v4h r;
-    r[0] = (_Float16)(float)g[0]; r[1] = (_Float16)(float)g[1];
-    r[2] = (_Float16)(float)g[2]; r[3] = (_Float16)(float)g[3];
+    r[0] = d2h(g[0]); r[1] = d2h(g[1]); r[2] = d2h(g[2]); r[3] = d2h(g[3]);
     return r;
 }
 
