@@ -53,12 +53,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 
-// bfloat16 bits of a float, rounded to nearest even (finite inputs).
+// bfloat16 bits of a float, rounded to nearest even on the hardware
+// converter; x is kept opaque so that a double -> float rounding before the
+// call is not folded into one double -> bfloat16 conversion (which has no
+// instruction and is expanded into a correction sequence)
 __device__ __forceinline__ short f2bf(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+    asm volatile("" : "+v"(x));
+    return (short)__builtin_bit_cast(uint16_t, (__bf16)x);
 }
 
 // Per precision: MFMA operand type, K steps and K per lane, accumulator and
