@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <atomic>
 #include <numeric>
 #include <thread>
@@ -275,16 +277,13 @@ void sfc_order(const std::vector<double> &pos, int dim, int64_t n, int32_t *perm
         for (int t = 0; t <= nt; ++t) cut.push_back(n * t / nt);
     }
     while (cut.size() > 2) {
+        const int nm = (int)((cut.size() - 1) / 2);   // pairs of neighbouring ranges merged this round
+        femk::run_jobs(nm, [&](int j) {
+            std::inplace_merge(key.begin() + cut[2 * j], key.begin() + cut[2 * j + 1], key.begin() + cut[2 * j + 2]);
+        });
         std::vector<int64_t> next{cut[0]};
-        std::vector<std::thread> pool;
-        for (size_t j = 0; j + 2 < cut.size(); j += 2) {
-            pool.emplace_back([&key, a = cut[j], m = cut[j + 1], e = cut[j + 2]]() {
-                std::inplace_merge(key.begin() + a, key.begin() + m, key.begin() + e);
-            });
-            next.push_back(cut[j + 2]);
-        }
+        for (int j = 0; j < nm; ++j) next.push_back(cut[2 * j + 2]);
         if (cut.size() % 2 == 0) next.push_back(cut.back());   // an odd range left over
-        for (std::thread &t : pool) t.join();
         cut.swap(next);
     }
     for (int64_t i = 0; i < n; ++i) perm[i] = key[i].second;
@@ -293,6 +292,22 @@ void sfc_order(const std::vector<double> &pos, int dim, int64_t n, int32_t *perm
 }  // namespace
 
 namespace femk {
+
+fem_status caught_status(fem_ctx *ctx, const char *where)
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = std::string(where) + ": host allocation failed";
+        return FEM_E_NOMEM;
+    } catch (const std::exception &e) {
+        if (ctx) ctx->err = std::string(where) + ": " + e.what();
+        return FEM_E_DEVICE;
+    } catch (...) {
+        if (ctx) ctx->err = std::string(where) + ": unexpected host error";
+        return FEM_E_DEVICE;
+    }
+}
 
 hipError_t mem_alloc(const fem_mem &m, hipStream_t s, bool temp, size_t bytes, void **p)
 {
@@ -689,8 +704,21 @@ void mat_streams(const StreamIn &in, int64_t r0, int64_t r1, int64_t v0, int64_t
 
 }  // namespace
 
+static fem_status plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args, const fem_sparsity *sp,
+                              fem_plan **out);
+
 fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args,
                            const fem_sparsity *sp, fem_plan **out)
+{
+    try {
+        return plan_create(ctx, form, args, sp, out);
+    } catch (...) {
+        return femk::caught_status(ctx, "plan_create");
+    }
+}
+
+static fem_status plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *args, const fem_sparsity *sp,
+                              fem_plan **out)
 {
     if (!ctx) return FEM_E_ARG;
     if (!out) return fail(ctx, FEM_E_ARG, "plan_create: NULL output");
@@ -874,17 +902,18 @@ fem_status fem_plan_create(fem_ctx *ctx, const fem_form *form, const fem_args *a
         in.nrows = nrows;
         std::vector<StreamOut> outs((size_t)b);
         std::atomic<int32_t> next{0};
-        auto work = [&]() {
-            StreamScratch w;
-            for (int32_t i; (i = next.fetch_add(1)) < b;)
-                mat_streams(in, mb_r0[i], mb_r1[i], mb_v0[i], mb_v1[i], bcell.data() + blk_cptr[i],
-                            blk_cptr[i + 1] - blk_cptr[i], w, outs[i]);
-        };
-        const int nt = std::min<int>(femk::host_threads(), b);
-        std::vector<std::thread> pool;
-        for (int t = 1; t < nt; ++t) pool.emplace_back(work);
-        work();
-        for (std::thread &t : pool) t.join();
+        std::atomic<bool> failed{false};
+        femk::run_jobs(std::min<int>(femk::host_threads(), b), [&](int) {
+            try {
+                StreamScratch w;
+                for (int32_t i; !failed && (i = next.fetch_add(1)) < b;)
+                    mat_streams(in, mb_r0[i], mb_r1[i], mb_v0[i], mb_v1[i], bcell.data() + blk_cptr[i],
+                                blk_cptr[i + 1] - blk_cptr[i], w, outs[i]);
+            } catch (...) {
+                failed = true;
+            }
+        });
+        if (failed) return fail(ctx, FEM_E_NOMEM, "plan_create: host allocation failed while building the streams");
         size_t total = 0;
         for (const StreamOut &o : outs) total += o.stream.size();
         stream.reserve(total);
@@ -1244,8 +1273,21 @@ fem_status fem_apply_dirichlet(fem_ctx *ctx, const fem_sparsity *sp, double *val
     return FEM_OK;
 }
 
+static fem_status renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args, int32_t *cell_perm,
+                           int32_t *vertex_perm, int32_t *node_perm);
+
 fem_status fem_renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args, int32_t *cell_perm,
                         int32_t *vertex_perm, int32_t *node_perm)
+{
+    try {
+        return renumber(ctx, form, args, cell_perm, vertex_perm, node_perm);
+    } catch (...) {
+        return femk::caught_status(ctx, "renumber");
+    }
+}
+
+static fem_status renumber(fem_ctx *ctx, const fem_form *form, const fem_args *args, int32_t *cell_perm,
+                           int32_t *vertex_perm, int32_t *node_perm)
 {
     if (!ctx) return FEM_E_ARG;
     fem_status st = check_form(ctx, form);

@@ -121,7 +121,18 @@ fem_status facet_check(fem_ctx *ctx, const fem_form *form, const fem_facets *fa)
 
 extern "C" {
 
+static fem_status fem_facet_plan_create_impl(fem_ctx *ctx, const fem_form *form, const fem_facets *fa, fem_plan **out);
+
 fem_status fem_facet_plan_create(fem_ctx *ctx, const fem_form *form, const fem_facets *fa, fem_plan **out)
+{
+    try {
+        return fem_facet_plan_create_impl(ctx, form, fa, out);
+    } catch (...) {
+        return femk::caught_status(ctx, "facet_plan_create");
+    }
+}
+
+static fem_status fem_facet_plan_create_impl(fem_ctx *ctx, const fem_form *form, const fem_facets *fa, fem_plan **out)
 {
     using namespace femk;
     if (!ctx) return FEM_E_ARG;

@@ -212,17 +212,39 @@ inline int host_threads()
     return (int)std::max(1u, std::min(16u, h));
 }
 
+// Runs job(t) for t in [0, nt): t = 0 on the calling thread, the others on
+// threads of their own (a job whose thread cannot be started runs on the
+// calling thread instead).  Every thread is joined before returning; a job
+// must not throw (jobs catch their own failures and report them).
+template <typename J>
+void run_jobs(int nt, J job)
+{
+    std::vector<std::thread> pool;
+    std::vector<int> inline_jobs;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(job, t);
+        } catch (...) {
+            inline_jobs.push_back(t);
+        }
+    }
+    job(0);
+    for (int t : inline_jobs) job(t);
+    for (std::thread &th : pool) th.join();
+}
+
 // Runs fn(lo, hi) over [0, n) split into contiguous ranges, one per host
-// thread (one range when n is small).
+// thread (one range when n is small); fn must not throw.
 template <typename F>
 void par_ranges(int64_t n, F fn)
 {
     const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / 65536));
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
-    fn((int64_t)0, n / nt);
-    for (std::thread &t : pool) t.join();
+    run_jobs(nt, [&](int t) { fn(n * t / nt, n * (t + 1) / nt); });
 }
+
+// The status of a C++ exception caught at the C boundary: host allocation
+// failures are FEM_E_NOMEM, anything else FEM_E_DEVICE.
+fem_status caught_status(fem_ctx *ctx, const char *where);
 
 
 }  // namespace femk

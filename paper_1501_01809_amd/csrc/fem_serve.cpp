@@ -171,7 +171,18 @@ static int64_t req_bytes(const Model &m, int op)
 
 extern "C" {
 
+static fem_status fem_server_create_impl(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fem_server **out);
+
 fem_status fem_server_create(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fem_server **out)
+{
+    try {
+        return fem_server_create_impl(ctx, slots, hbm_budget, out);
+    } catch (...) {
+        return femk::caught_status(ctx, "server_create");
+    }
+}
+
+static fem_status fem_server_create_impl(fem_ctx *ctx, int32_t slots, int64_t hbm_budget, fem_server **out)
 {
     if (!ctx) return FEM_E_ARG;
     if (!out || slots < 1 || slots > 64 || hbm_budget <= 0)
@@ -225,7 +236,20 @@ void fem_server_destroy(fem_server *s)
     delete s;
 }
 
+static fem_status fem_server_add_model_impl(fem_server *s, const fem_form *form, const fem_args *args, int32_t *model_id,
+                                int64_t *resident_bytes);
+
 fem_status fem_server_add_model(fem_server *s, const fem_form *form, const fem_args *args, int32_t *model_id,
+                                int64_t *resident_bytes)
+{
+    try {
+        return fem_server_add_model_impl(s, form, args, model_id, resident_bytes);
+    } catch (...) {
+        return femk::caught_status(s ? s->ctx : nullptr, "server_add_model");
+    }
+}
+
+static fem_status fem_server_add_model_impl(fem_server *s, const fem_form *form, const fem_args *args, int32_t *model_id,
                                 int64_t *resident_bytes)
 {
     if (!s) return FEM_E_ARG;
@@ -289,7 +313,20 @@ fem_status fem_server_add_model(fem_server *s, const fem_form *form, const fem_a
     return FEM_OK;
 }
 
+static fem_status fem_server_submit_impl(fem_server *s, int32_t model, int32_t op, const double *x, double arrival_time,
+                             int64_t *req_id);
+
 fem_status fem_server_submit(fem_server *s, int32_t model, int32_t op, const double *x, double arrival_time,
+                             int64_t *req_id)
+{
+    try {
+        return fem_server_submit_impl(s, model, op, x, arrival_time, req_id);
+    } catch (...) {
+        return femk::caught_status(s ? s->ctx : nullptr, "server_submit");
+    }
+}
+
+static fem_status fem_server_submit_impl(fem_server *s, int32_t model, int32_t op, const double *x, double arrival_time,
                              int64_t *req_id)
 {
     if (!s) return FEM_E_ARG;
@@ -358,7 +395,18 @@ static fem_status launch_batch_on(fem_server *s, int slot, const std::vector<int
     return FEM_OK;
 }
 
+static fem_status fem_server_poll_impl(fem_server *s, double now, int32_t *completed, int32_t *running, int32_t *queued);
+
 fem_status fem_server_poll(fem_server *s, double now, int32_t *completed, int32_t *running, int32_t *queued)
+{
+    try {
+        return fem_server_poll_impl(s, now, completed, running, queued);
+    } catch (...) {
+        return femk::caught_status(s ? s->ctx : nullptr, "server_poll");
+    }
+}
+
+static fem_status fem_server_poll_impl(fem_server *s, double now, int32_t *completed, int32_t *running, int32_t *queued)
 {
     if (!s) return FEM_E_ARG;
     fem_ctx *ctx = s->ctx;
