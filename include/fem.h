@@ -303,7 +303,11 @@ fem_status fem_expand_sparsity(fem_ctx *ctx, const fem_sparsity *node, int32_t b
  * contribution to its rows in an order fixed by the plan (conflict-free INC without
  * atomics; "Access descriptors": only INC needs a schedule).  It references
  * the Maps' device arrays: rebuild it if their contents change.  Synchronises;
- * allocates device memory owned by the plan.
+ * allocates device memory owned by the plan.  A Mat row with more values than
+ * one block holds in LDS is split into blocks of consecutive value slices;
+ * FEM_E_UNSUPPORTED if the cells of one row of a Dat plan do not fit one
+ * block.  FEM_E_ARG if the sparsity lacks an entry the Maps reach;
+ * FEM_E_NOMEM if a device or host allocation fails.
  *
  * FEM_ELASTICITY plans (sp = the vector CSR, the 3x3-block expansion of the
  * node sparsity, e.g. from fem_expand_sparsity) hold, per node pair, the
