@@ -17,8 +17,9 @@
 // (cell, ab) columns for every 16 cells, K = 36 (FP64/FP32: 9 steps of 4;
 // BF16/FP16: 3 steps of 16, K padded to 48).  For the narrow types G is
 // scaled per cell by a power of two (exact) that brings its entries to
-// magnitude <= 1, and the FP32 accumulator is scaled back; accumulation is in
-// FP32 (FP64 for the FP64 path).  The blocks (i <= j, 3 x 3 each) go to a
+// magnitude <= 1, and the FP32 accumulator is scaled back (FP16 stores it as
+// it is, with the scale's exponent); accumulation is in FP32 (FP64 for the
+// FP64 path).  The blocks (i <= j, 3 x 3 each) go to a
 // plan-owned workspace E[cell][pair][a*3+b] (FP64; FP32 for the FP32
 // contraction; 16-bit values, ten per block, for BF16 and FP16).
 //
@@ -112,14 +113,14 @@ template <> struct WsOf<FEM_FP64> { typedef double T; };
 template <> struct WsOf<FEM_BF16> { typedef uint16_t T; };
 template <> struct WsOf<FEM_FP16> { typedef half_ws T; };
 // Stores entry ab of a block (E the block's first element); acc is the
-// contraction's accumulator, scale = 2^sexp the cell's operand scale.
-__device__ __forceinline__ void ws_put(double *E, int ab, double acc, double scale, int) { E[ab] = acc * scale; }
-__device__ __forceinline__ void ws_put(float *E, int ab, float acc, double scale, int) { E[ab] = acc * (float)scale; }
-__device__ __forceinline__ void ws_put(uint16_t *E, int ab, float acc, double scale, int)
+// contraction's accumulator and scale the cell's power-of-two operand scale.
+__device__ __forceinline__ void ws_put(double *E, int ab, double acc, double scale) { E[ab] = acc * scale; }
+__device__ __forceinline__ void ws_put(float *E, int ab, float acc, double scale) { E[ab] = acc * (float)scale; }
+__device__ __forceinline__ void ws_put(uint16_t *E, int ab, float acc, double scale)
 {
     E[ab] = (uint16_t)f2bf(acc * (float)scale);
 }
-__device__ __forceinline__ void ws_put(half_ws *E, int ab, float acc, double, int)
+__device__ __forceinline__ void ws_put(half_ws *E, int ab, float acc, double)
 {
     E[ab].bits = __builtin_bit_cast(uint16_t, (_Float16)acc);   // (the exponent: after the tiles)
 }
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(EWG) void k_elast_element(ElArgs a)
                 for (int v = 0; v < 4; ++v) {
                     const int pr = 16 * mt + M::row(lane, v);
                     if (live && pr < NP)
-                        ws_put(E + cell * (NP * BS) + pr * BS, ab, acc[v], scale, 0);
+                        ws_put(E + cell * (NP * BS) + pr * BS, ab, acc[v], scale);
                 }
             }
         }
