@@ -938,6 +938,12 @@ static fem_status plan_create(fem_ctx *ctx, const fem_form *form, const fem_args
 
     fem_plan *p = new (std::nothrow) fem_plan;
     if (!p) return fail(ctx, FEM_E_NOMEM, "plan_create: host allocation");
+    // frees the plan and the arrays uploaded so far on every way out but
+    // success (an error status or a host allocation failure below)
+    struct Release {
+        fem_plan *p;
+        ~Release() { if (p) { free_plan_arrays(p); delete p; } }
+    } release{p};
     p->is_mat = is_mat;
     p->dim = dim; p->degree = deg; p->nloc = nl;
     p->ncells = ncells; p->nrows = nrows; p->nverts = args->cell_vertex->to->size;
@@ -993,11 +999,8 @@ static fem_status plan_create(fem_ctx *ctx, const fem_form *form, const fem_args
         if (e == hipSuccess) e = upload(p->mem, &p->pstream, stream, &p->bytes, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        free_plan_arrays(p);
-        delete p;
-        return hip_fail(ctx, e, "plan_create");
-    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "plan_create");
+    release.p = nullptr;
     *out = p;
     return FEM_OK;
 }
